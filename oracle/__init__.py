@@ -1,0 +1,19 @@
+"""FP64 CPU oracle for the near-field force (test infrastructure only).
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  It shares no code with the HIP library.
+"""
+from .oracle import (  # noqa: F401
+    OracleError,
+    build,
+    lib_path,
+    cells,
+    bin_particles,
+    accel,
+    jvp,
+    vjp,
+    interactions,
+    num_threads,
+    set_num_threads,
+)
+from .brute import brute_accel  # noqa: F401
