@@ -1,0 +1,170 @@
+/*
+ * nf.h -- C ABI of the MI355X near-field force library (libnf.so).
+ *
+ * The library computes the near-field part of the compact near/far force
+ * split of Garrison, Eisenstein & Pinto (arXiv:1810.02916):
+ *
+ *   Sec. 2.1  A periodic box of side L is cut into K^3 cubic cells and every
+ *             particle belongs to exactly one cell.  Particles whose cells are
+ *             at most R = 2 cells apart on every axis (the 5x5x5 block of cells
+ *             around a particle's own cell) interact by direct pairwise
+ *             summation.  Positions are kept as single-precision offsets from
+ *             the centre of their cell.
+ *   Sec. 4.3  The pair force is the spline-softened law of Eq. 2,
+ *               F(r) = [10 - 15 (r/e) + 6 (r/e)^2] r / e^3   (r <  e)
+ *               F(r) = r / |r|^3                            (r >= e)
+ *             with e = eps_s, the spline radius.  The paper picks a
+ *             Plummer-equivalent length eps_p and uses eps_s = 2.16 eps_p; this
+ *             ABI takes eps_s itself.
+ *   Sec. 4.5  The near field is an exact sum whose only error is floating-point
+ *             round-off.
+ *
+ * Conventions fixed by this library where the paper is silent:
+ *   - a_i = gm * sum_{j in N(i)} F(x_j - x_i), so the force is attractive and
+ *     gm = G * m_particle (all particles have equal mass).
+ *   - a coincident pair (r = 0, the self pair included) contributes zero.
+ *   - cell of a coordinate x: s = x * (K / L) in double precision,
+ *     c = floor(s) mod K, offset o = (s - floor(s)) - 1/2 in cell widths,
+ *     rounded to float (round to nearest even).  Any finite real x is legal;
+ *     it is wrapped into the box.
+ *   - linear cell id = (cx * K + cy) * K + cz.
+ *
+ * Memory: every pointer inside nf_box and every array argument of the compute
+ * entry points is a DEVICE pointer owned by the caller.  The library allocates
+ * no device memory; temporary storage comes from the caller's workspace, sized
+ * by nf_workspace_bytes().  `stream` is a hipStream_t (NULL = null stream).
+ * All work is enqueued asynchronously on that stream.
+ *
+ * Errors: arguments are validated on the host before anything is enqueued.
+ * On a non-zero return nothing has been enqueued and no output is touched;
+ * nf_last_error() gives a thread-local description.  NF_EHIP reports a HIP
+ * launch error (the stream may then hold part of the work).  Faults that
+ * happen while kernels run surface at the caller's next synchronisation.
+ * No C++ exception crosses this interface.
+ *
+ * Determinism: for fixed inputs, flags and device the outputs are bitwise
+ * reproducible (stable binning, fixed summation order, no float atomics).
+ */
+#ifndef NF_H
+#define NF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NF_ABI_VERSION 1
+
+/* Status codes. */
+enum {
+    NF_OK = 0,
+    NF_EINVAL = 1,        /* an argument is out of range or a pointer is NULL */
+    NF_EWORKSPACE = 2,    /* workspace NULL or smaller than nf_workspace_bytes() */
+    NF_EHIP = 3,          /* a HIP runtime call failed */
+    NF_EUNSUPPORTED = 4   /* sizes beyond the 32-bit index range, or a device
+                             that is not gfx950 */
+};
+
+/* Flags for nf_accel / nf_accel_vjp. */
+enum {
+    /* Compensated (Kahan) per-sink accumulation.  Sec. 4.5 names round-off
+       in the accumulation of accelerations as the main error source of the
+       single-precision near field; this removes it. */
+    NF_COMPENSATED = 1u << 0,
+    /* Reference kernel: one sink per thread, sources read straight from
+       global memory.  Same arithmetic, slower; kept for cross-checks. */
+    NF_SIMPLE = 1u << 1
+};
+
+/* Upper bound on boxes per call. */
+#define NF_MAX_BOXES 4096
+
+/*
+ * One periodic box.  Layouts:
+ *   pos         [n][3] double, caller (input) order.  Read by nf_bin_particles.
+ *   off         [n][4] float, cell-sorted: (ox, oy, oz, 0), the offsets of
+ *               Sec. 2.1 in cell widths, each in [-1/2, 1/2].
+ *               Written by nf_bin_particles, read by nf_accel / nf_accel_vjp.
+ *   cell_start  [K^3 + 1] int32: sorted slots of cell c are
+ *               cell_start[c] .. cell_start[c+1]-1; cell_start[K^3] = n.
+ *   order       [n] int32: input index of each sorted slot.  Within a cell,
+ *               slots are in increasing input index (stable sort).
+ *   nbad        optional [1] int32 (may be NULL): nf_bin_particles stores the
+ *               number of particles with a non-finite coordinate, or one so
+ *               large that s = x K / L has magnitude >= 2^62.  Such particles
+ *               are binned into cell 0 at offset 0 and every force computed
+ *               for that box is then meaningless; the caller must check it.
+ * Requirements: n >= 0, 5 <= K (K = 2R+1 with R = 2; smaller grids would
+ * alias the 5x5x5 block), K^3 + 1 <= 2^31 - 1, n <= 2^31 - 1, L and eps_s
+ * finite and > 0.  Pointers may be NULL only when n == 0 (cell_start never).
+ */
+typedef struct nf_box {
+    int64_t n;
+    int32_t K;
+    int32_t reserved;   /* set to 0 */
+    double L;
+    double eps_s;
+    const double *pos;
+    float *off;
+    int32_t *cell_start;
+    int32_t *order;
+    int32_t *nbad;
+} nf_box;
+
+/* Library version (NF_ABI_VERSION). */
+int nf_version(void);
+
+/* Static text for a status code. */
+const char *nf_strerror(int status);
+
+/* Thread-local description of the last failure of this thread ("" if none). */
+const char *nf_last_error(void);
+
+/*
+ * Bytes of workspace that nf_bin_particles, nf_accel and nf_accel_vjp need
+ * for this set of boxes and flags.  The same workspace serves all three
+ * (calls on one stream run in order; overlapping calls need separate
+ * workspaces).  Returns 0 and sets nf_last_error() if the boxes are invalid.
+ */
+size_t nf_workspace_bytes(int nbox, const nf_box *boxes, uint32_t flags);
+
+/*
+ * Binning (Sec. 2.1): for each box, assign every particle to its cell,
+ * compute its centre offset, and sort particles by cell (stable).
+ * Writes off, cell_start, order (and nbad) of every box.
+ * Work: about 40 bytes of HBM traffic per particle per radix pass.
+ */
+int nf_bin_particles(int nbox, const nf_box *boxes, void *ws, size_t ws_bytes,
+                     void *stream);
+
+/*
+ * Near-field accelerations (Sec. 2.1 direct sum, Sec. 4.3 Eq. 2):
+ *   acc[b][i] = gm * sum_{j in N(i)} F(x_j - x_i)     (length / time^2 units
+ *   of gm / L^2), float, [n_b][3] in caller order.
+ * Requires the boxes as filled by nf_bin_particles (off, cell_start, order);
+ * pos is not read.  acc is an array of nbox device pointers (host array).
+ * Arithmetic: FP32 on cell offsets; flags may add NF_COMPENSATED.
+ */
+int nf_accel(int nbox, const nf_box *boxes, double gm, uint32_t flags,
+             float *const *acc, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Vector-Jacobian product of the accelerations with respect to positions,
+ * with the cell assignment held fixed (the derivative is taken inside a cell
+ * assignment; it is the derivative of the same sum of Eq. 2 terms):
+ *   grad[b][k] = sum_i (d a_i / d x_k)^T cot[b][i]
+ *              = gm * kappa^3 * sum_{j in N(k)} J(r_kj) (cot_j - cot_k),
+ * where kappa = K/L and J(r) = dF/dr (cell units) is the 3x3 Jacobian of Eq. 2.
+ * cot and grad: nbox device pointers each to [n_b][3] float, caller order.
+ */
+int nf_accel_vjp(int nbox, const nf_box *boxes, double gm, uint32_t flags,
+                 const float *const *cot, float *const *grad, void *ws,
+                 size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NF_H */

@@ -1,0 +1,329 @@
+// nf_api.hip -- host side of the C ABI declared in include/nf.h: argument
+// validation, workspace layout, descriptor upload and kernel dispatch.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "nf.h"
+#include "nf_internal.h"
+#include "nf_kernels.h"
+
+namespace nf {
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string &msg) {
+    g_last_error = msg;
+    return code;
+}
+
+// Descriptor bytes travel as a kernel argument (no host-to-device memcpy), so
+// every call is a pure sequence of kernel launches.
+constexpr int kChunkBytes = 2048;
+struct Chunk {
+    unsigned char bytes[kChunkBytes];
+};
+
+__global__ void k_put_bytes(Chunk c, unsigned char *dst, int nbytes) {
+    for (int i = threadIdx.x; i < nbytes; i += blockDim.x) dst[i] = c.bytes[i];
+}
+
+hipError_t upload(const void *src, size_t nbytes, void *dst, hipStream_t s) {
+    const unsigned char *p = static_cast<const unsigned char *>(src);
+    unsigned char *d = static_cast<unsigned char *>(dst);
+    for (size_t o = 0; o < nbytes; o += kChunkBytes) {
+        Chunk c;
+        int m = (int)std::min<size_t>(kChunkBytes, nbytes - o);
+        std::memcpy(c.bytes, p + o, (size_t)m);
+        hipLaunchKernelGGL(k_put_bytes, dim3(1), dim3(256), 0, s, c, d + o, m);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Device architecture check, cached per device.
+std::mutex g_dev_mu;
+std::vector<int> g_dev_ok;   // -1 unknown, 0 no, 1 yes
+
+int check_device(std::string &why) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        why = std::string("hipGetDevice: ") + hipGetErrorString(e);
+        return NF_EHIP;
+    }
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    if ((int)g_dev_ok.size() <= dev) g_dev_ok.resize(dev + 1, -1);
+    if (g_dev_ok[dev] < 0) {
+        hipDeviceProp_t prop;
+        e = hipGetDeviceProperties(&prop, dev);
+        if (e != hipSuccess) {
+            why = std::string("hipGetDeviceProperties: ") + hipGetErrorString(e);
+            return NF_EHIP;
+        }
+        g_dev_ok[dev] = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0 ? 1 : 0;
+        if (!g_dev_ok[dev]) why = std::string("device is ") + prop.gcnArchName + ", not gfx950";
+    }
+    if (!g_dev_ok[dev]) {
+        if (why.empty()) why = "device is not gfx950";
+        return NF_EUNSUPPORTED;
+    }
+    return NF_OK;
+}
+
+// Validated sizes of a call.
+struct Layout {
+    int64_t N = 0, C = 0, max_n = 0, max_ncell = 0;
+    std::vector<int64_t> base, cellbase;
+    // workspace byte offsets
+    size_t table_off = 0, table_bytes = 0;
+    size_t keys_off[2] = {0, 0}, vals_off[2] = {0, 0};
+    size_t hist_off = 0, cellcnt_off = 0, scan_off = 0;
+    size_t cot_off = 0;
+    size_t total = 0;
+    int64_t nblk = 0;
+    int passes = 0;
+};
+
+int validate(int nbox, const nf_box *boxes, Layout &L) {
+    if (nbox < 1 || nbox > NF_MAX_BOXES)
+        return fail(NF_EINVAL, "nbox must be in [1, NF_MAX_BOXES]");
+    if (!boxes) return fail(NF_EINVAL, "boxes is NULL");
+    L.base.resize(nbox);
+    L.cellbase.resize(nbox);
+    for (int b = 0; b < nbox; ++b) {
+        const nf_box &B = boxes[b];
+        char where[64];
+        std::snprintf(where, sizeof where, "box %d: ", b);
+        if (B.n < 0) return fail(NF_EINVAL, std::string(where) + "n < 0");
+        if (B.K < 5) return fail(NF_EINVAL, std::string(where) + "K < 5 (the 5x5x5 block would alias)");
+        if (!(B.L > 0) || !std::isfinite(B.L)) return fail(NF_EINVAL, std::string(where) + "L must be finite and > 0");
+        if (!(B.eps_s > 0) || !std::isfinite(B.eps_s))
+            return fail(NF_EINVAL, std::string(where) + "eps_s must be finite and > 0");
+        const int64_t ncell = (int64_t)B.K * B.K * B.K;
+        if (ncell + 1 > INT32_MAX) return fail(NF_EUNSUPPORTED, std::string(where) + "K^3 + 1 exceeds 2^31 - 1");
+        if (B.n > INT32_MAX) return fail(NF_EUNSUPPORTED, std::string(where) + "n exceeds 2^31 - 1");
+        if (!B.cell_start) return fail(NF_EINVAL, std::string(where) + "cell_start is NULL");
+        if (B.n > 0 && (!B.off || !B.order))
+            return fail(NF_EINVAL, std::string(where) + "off/order is NULL");
+        const double kappa = (double)B.K / B.L;
+        if (!std::isfinite(kappa) || !std::isfinite(B.eps_s * kappa) || !(B.eps_s * kappa > 0))
+            return fail(NF_EINVAL, std::string(where) + "K/L or eps_s*K/L is not a positive finite number");
+        L.base[b] = L.N;
+        L.cellbase[b] = L.C;
+        L.N += B.n;
+        L.C += ncell;
+        L.max_n = std::max<int64_t>(L.max_n, B.n);
+        L.max_ncell = std::max<int64_t>(L.max_ncell, ncell);
+    }
+    if (L.N > INT32_MAX) return fail(NF_EUNSUPPORTED, "total particles over all boxes exceed 2^31 - 1");
+    if (L.C + 1 > INT32_MAX) return fail(NF_EUNSUPPORTED, "total cells over all boxes exceed 2^31 - 2");
+    int bits = 1;
+    while (bits < 32 && ((int64_t)1 << bits) < L.C) ++bits;
+    L.passes = (bits + kRadixBits - 1) / kRadixBits;
+    L.nblk = std::max<int64_t>(1, (L.N + kSortTile - 1) / kSortTile);
+
+    size_t o = 0;
+    L.table_off = o;
+    L.table_bytes = sizeof(DevBox) * (size_t)nbox;
+    o = align_up(o + L.table_bytes, 256);
+    const size_t scratch0 = o;
+    for (int k = 0; k < 2; ++k) {
+        L.keys_off[k] = o;
+        o = align_up(o + 4 * (size_t)L.N, 256);
+        L.vals_off[k] = o;
+        o = align_up(o + 4 * (size_t)L.N, 256);
+    }
+    L.hist_off = o;
+    o = align_up(o + 4 * (size_t)kRadix * (size_t)L.nblk, 256);
+    L.cellcnt_off = o;
+    o = align_up(o + 4 * (size_t)(L.C + 1), 256);
+    L.scan_off = o;
+    const int64_t scan_words =
+        std::max(scan_scratch_words((int64_t)kRadix * L.nblk), scan_scratch_words(L.C + 1));
+    o = align_up(o + 4 * (size_t)scan_words, 256);
+    const size_t bin_end = o;
+    // force scratch reuses the binning scratch region
+    o = scratch0;
+    L.cot_off = o;
+    o = align_up(o + 16 * (size_t)L.N, 256);
+    L.total = std::max(bin_end, o);
+    return NF_OK;
+}
+
+int check_ws(const Layout &L, void *ws, size_t ws_bytes) {
+    if (!ws) return fail(NF_EWORKSPACE, "workspace is NULL");
+    if (ws_bytes < L.total) {
+        char m[128];
+        std::snprintf(m, sizeof m, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
+        return fail(NF_EWORKSPACE, m);
+    }
+    if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(NF_EWORKSPACE, "workspace must be 256-byte aligned");
+    return NF_OK;
+}
+
+void fill_geometry(const nf_box &B, const Layout &L, int b, DevBox &d) {
+    std::memset(&d, 0, sizeof d);
+    d.n = (int32_t)B.n;
+    d.K = B.K;
+    d.ncell = B.K * B.K * B.K;
+    d.base = L.base[b];
+    d.cellbase = L.cellbase[b];
+    d.kappa = (double)B.K / B.L;
+    const double eps = B.eps_s * d.kappa;
+    d.eps = (float)eps;
+    d.cA = (float)(10.0 / (eps * eps * eps));
+    d.cB = (float)(-15.0 / (eps * eps * eps * eps));
+    d.cC = (float)(6.0 / (eps * eps * eps * eps * eps));
+    d.outer_newton = eps <= 1.0 ? 1 : 0;
+    d.pos = B.pos;
+    d.off = reinterpret_cast<float4 *>(B.off);
+    d.cell_start = B.cell_start;
+    d.order = B.order;
+    d.nbad = B.nbad;
+}
+
+}  // namespace
+}  // namespace nf
+
+using namespace nf;
+
+extern "C" {
+
+int nf_version(void) { return NF_ABI_VERSION; }
+
+const char *nf_strerror(int status) {
+    switch (status) {
+        case NF_OK: return "success";
+        case NF_EINVAL: return "invalid argument";
+        case NF_EWORKSPACE: return "workspace missing or too small";
+        case NF_EHIP: return "HIP runtime error";
+        case NF_EUNSUPPORTED: return "unsupported size or device";
+        default: return "unknown status";
+    }
+}
+
+const char *nf_last_error(void) { return g_last_error.c_str(); }
+
+size_t nf_workspace_bytes(int nbox, const nf_box *boxes, uint32_t flags) {
+    (void)flags;
+    try {
+        Layout L;
+        if (validate(nbox, boxes, L) != NF_OK) return 0;
+        g_last_error.clear();
+        return L.total;
+    } catch (...) {
+        fail(NF_EINVAL, "internal error");
+        return 0;
+    }
+}
+
+int nf_bin_particles(int nbox, const nf_box *boxes, void *ws, size_t ws_bytes, void *stream) {
+    try {
+        Layout L;
+        int rc = validate(nbox, boxes, L);
+        if (rc) return rc;
+        for (int b = 0; b < nbox; ++b)
+            if (boxes[b].n > 0 && !boxes[b].pos) return fail(NF_EINVAL, "pos is NULL");
+        if ((rc = check_ws(L, ws, ws_bytes))) return rc;
+        std::string why;
+        if ((rc = check_device(why))) return fail(rc, why);
+        std::vector<DevBox> tab((size_t)nbox);
+        for (int b = 0; b < nbox; ++b) fill_geometry(boxes[b], L, b, tab[b]);
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        char *w = static_cast<char *>(ws);
+        DevBox *d_tab = reinterpret_cast<DevBox *>(w + L.table_off);
+        hipError_t e = upload(tab.data(), sizeof(DevBox) * tab.size(), d_tab, s);
+        if (e != hipSuccess) return fail(NF_EHIP, std::string("upload: ") + hipGetErrorString(e));
+        BinPlan p;
+        p.N = L.N;
+        p.C = L.C;
+        p.max_n = L.max_n;
+        p.max_ncell = L.max_ncell;
+        p.nblk = L.nblk;
+        p.passes = L.passes;
+        for (int k = 0; k < 2; ++k) {
+            p.sc.keys[k] = reinterpret_cast<uint32_t *>(w + L.keys_off[k]);
+            p.sc.vals[k] = reinterpret_cast<uint32_t *>(w + L.vals_off[k]);
+        }
+        p.sc.hist = reinterpret_cast<uint32_t *>(w + L.hist_off);
+        p.sc.cellcnt = reinterpret_cast<uint32_t *>(w + L.cellcnt_off);
+        p.scan_scratch = reinterpret_cast<uint32_t *>(w + L.scan_off);
+        e = bin_launch(d_tab, nbox, p, s);
+        if (e != hipSuccess) return fail(NF_EHIP, std::string("bin launch: ") + hipGetErrorString(e));
+        g_last_error.clear();
+        return NF_OK;
+    } catch (...) {
+        return fail(NF_EINVAL, "internal error");
+    }
+}
+
+static int force_common(int nbox, const nf_box *boxes, double gm, uint32_t flags,
+                        const float *const *cot, float *const *out, void *ws, size_t ws_bytes,
+                        void *stream, bool vjp) {
+    Layout L;
+    int rc = validate(nbox, boxes, L);
+    if (rc) return rc;
+    if (!std::isfinite(gm)) return fail(NF_EINVAL, "gm must be finite");
+    if (flags & ~(uint32_t)(NF_COMPENSATED | NF_SIMPLE)) return fail(NF_EINVAL, "unknown flag bits");
+    if (!out) return fail(NF_EINVAL, "output pointer array is NULL");
+    if (vjp && !cot) return fail(NF_EINVAL, "cotangent pointer array is NULL");
+    for (int b = 0; b < nbox; ++b) {
+        if (boxes[b].n > 0 && !out[b]) return fail(NF_EINVAL, "output pointer is NULL");
+        if (vjp && boxes[b].n > 0 && !cot[b]) return fail(NF_EINVAL, "cotangent pointer is NULL");
+    }
+    if ((rc = check_ws(L, ws, ws_bytes))) return rc;
+    std::string why;
+    if ((rc = check_device(why))) return fail(rc, why);
+    std::vector<DevBox> tab((size_t)nbox);
+    for (int b = 0; b < nbox; ++b) {
+        fill_geometry(boxes[b], L, b, tab[b]);
+        const double k = tab[b].kappa;
+        tab[b].scale = (float)(vjp ? gm * k * k * k : gm * k * k);
+        tab[b].out = out[b];
+        tab[b].cot = vjp ? cot[b] : nullptr;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char *w = static_cast<char *>(ws);
+    DevBox *d_tab = reinterpret_cast<DevBox *>(w + L.table_off);
+    hipError_t e = upload(tab.data(), sizeof(DevBox) * tab.size(), d_tab, s);
+    if (e != hipSuccess) return fail(NF_EHIP, std::string("upload: ") + hipGetErrorString(e));
+    ForcePlan p;
+    p.max_n = L.max_n;
+    p.N = L.N;
+    p.compensated = (flags & NF_COMPENSATED) != 0;
+    p.simple = (flags & NF_SIMPLE) != 0;
+    p.cot_sorted = reinterpret_cast<float4 *>(w + L.cot_off);
+    e = vjp ? vjp_launch(d_tab, nbox, p, s) : accel_launch(d_tab, nbox, p, s);
+    if (e != hipSuccess) return fail(NF_EHIP, std::string("force launch: ") + hipGetErrorString(e));
+    g_last_error.clear();
+    return NF_OK;
+}
+
+int nf_accel(int nbox, const nf_box *boxes, double gm, uint32_t flags, float *const *acc,
+             void *ws, size_t ws_bytes, void *stream) {
+    try {
+        return force_common(nbox, boxes, gm, flags, nullptr, acc, ws, ws_bytes, stream, false);
+    } catch (...) {
+        return fail(NF_EINVAL, "internal error");
+    }
+}
+
+int nf_accel_vjp(int nbox, const nf_box *boxes, double gm, uint32_t flags,
+                 const float *const *cot, float *const *grad, void *ws, size_t ws_bytes,
+                 void *stream) {
+    try {
+        return force_common(nbox, boxes, gm, flags, cot, grad, ws, ws_bytes, stream, true);
+    } catch (...) {
+        return fail(NF_EINVAL, "internal error");
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,296 @@
+// nf_bin.hip -- binning of particles into the K^3 cell grid (Sec. 2.1):
+// cell index + centre offset in double precision, then a stable sort by cell.
+//
+// All boxes of one call are binned together: box b's keys live in their own
+// range [cellbase_b, cellbase_b + K_b^3) of one concatenated key space, so a
+// single stable LSD radix sort over the concatenation of all boxes leaves
+// every box's particles in its own slice, sorted by cell, ties in input order.
+#include "nf_internal.h"
+#include "nf_kernels.h"
+
+namespace nf {
+
+// ---------------------------------------------------------------- utilities
+
+__global__ void k_fill_u32(uint32_t *p, int64_t count, uint32_t value) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < count; i += stride) p[i] = value;
+}
+
+// Zero each box's bad-particle counter.
+__global__ void k_bin_zero_status(const DevBox *boxes, int nbox) {
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < nbox && boxes[b].nbad) boxes[b].nbad[0] = 0;
+}
+
+// ------------------------------------------------------------- cell keys
+
+// One thread per particle: linear cell id (in the box's key range) and its
+// concatenated element index; atomically counts particles per cell.
+__global__ void __launch_bounds__(256) k_bin_keys(const DevBox *boxes, BinScratch sc) {
+    const DevBox &B = boxes[blockIdx.y];
+    int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= B.n) return;
+    int c[3];
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double o;
+        ok &= cell_coord(B.pos[3 * (int64_t)i + a], B.kappa, B.K, c[a], o);
+    }
+    if (!ok) {
+        c[0] = c[1] = c[2] = 0;
+        if (B.nbad) atomicAdd(B.nbad, 1);
+    }
+    uint32_t key = (uint32_t)B.cellbase + (uint32_t)((c[0] * B.K + c[1]) * B.K + c[2]);
+    int64_t g = B.base + i;
+    sc.keys[0][g] = key;
+    sc.vals[0][g] = (uint32_t)g;
+    atomicAdd(&sc.cellcnt[key], 1u);
+}
+
+// ------------------------------------------------------------- radix sort
+
+// Per-tile digit histogram, written digit-major: hist[d * nblk + tile].
+__global__ void __launch_bounds__(kSortThreads)
+k_radix_hist(const uint32_t *__restrict__ keys, int64_t N, int shift, int nblk,
+             uint32_t *__restrict__ hist) {
+    __shared__ uint32_t cnt[kRadix];
+    const int t = threadIdx.x;
+    cnt[t] = 0;
+    __syncthreads();
+    const int w = t >> 6, lane = t & 63;
+    const int64_t base = (int64_t)blockIdx.x * kSortTile + w * (kSortTile / 4);
+#pragma unroll 4
+    for (int k = 0; k < kSortItems; ++k) {
+        int64_t idx = base + k * 64 + lane;
+        bool valid = idx < N;
+        uint32_t d = valid ? ((keys[idx] >> shift) & (kRadix - 1)) : 0u;
+        uint64_t m = match_digit(valid, d);
+        if (valid && lane == 63 - __clzll(m)) atomicAdd(&cnt[d], (uint32_t)__popcll(m));
+    }
+    __syncthreads();
+    hist[(int64_t)t * nblk + blockIdx.x] = cnt[t];
+}
+
+// Stable scatter of one tile.  Wave w owns the contiguous quarter
+// [w*1024, (w+1)*1024) of the tile and walks it in rounds of 64, so
+// "earlier round, then lower lane, then lower wave" is input order.
+__global__ void __launch_bounds__(kSortThreads)
+k_radix_scatter(const uint32_t *__restrict__ keys_in, const uint32_t *__restrict__ vals_in,
+                uint32_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out,
+                int64_t N, int shift, int nblk, const uint32_t *__restrict__ hist_scan) {
+    __shared__ uint32_t gbase[kRadix];
+    __shared__ uint32_t wcnt[4][kRadix];
+    const int t = threadIdx.x;
+    const int w = t >> 6, lane = t & 63;
+    gbase[t] = hist_scan[(int64_t)t * nblk + blockIdx.x];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) wcnt[q][t] = 0;
+    __syncthreads();
+
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int64_t base = (int64_t)blockIdx.x * kSortTile + w * (kSortTile / 4);
+    uint32_t kk[kSortItems], vv[kSortItems], rk[kSortItems];
+#pragma unroll
+    for (int k = 0; k < kSortItems; ++k) {
+        int64_t idx = base + k * 64 + lane;
+        bool valid = idx < N;
+        uint32_t key = valid ? keys_in[idx] : 0u;
+        uint32_t val = valid ? vals_in[idx] : 0u;
+        uint32_t d = (key >> shift) & (kRadix - 1);
+        uint64_t m = match_digit(valid, d);
+        uint32_t before = wcnt[w][d];
+        __builtin_amdgcn_wave_barrier();
+        rk[k] = before + (uint32_t)__popcll(m & below);
+        if (valid && lane == 63 - __clzll(m)) wcnt[w][d] = before + (uint32_t)__popcll(m);
+        __builtin_amdgcn_wave_barrier();
+        kk[k] = key;
+        vv[k] = val;
+    }
+    __syncthreads();
+    {   // exclusive prefix of the per-wave digit counts over waves
+        uint32_t s = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            uint32_t c = wcnt[q][t];
+            wcnt[q][t] = s;
+            s += c;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kSortItems; ++k) {
+        int64_t idx = base + k * 64 + lane;
+        if (idx < N) {
+            uint32_t d = (kk[k] >> shift) & (kRadix - 1);
+            uint32_t dst = gbase[d] + wcnt[w][d] + rk[k];
+            if (dst < (uint64_t)N) {   // always true for a consistent histogram
+                keys_out[dst] = kk[k];
+                vals_out[dst] = vv[k];
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------- exclusive scan
+
+// Block-wide exclusive scan of 256 thread totals; returns this thread's prefix
+// and the block total.
+__device__ __forceinline__ uint32_t block_exclusive(uint32_t v, uint32_t &total) {
+    __shared__ uint32_t wsum[kScanThreads / 64];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    uint32_t wpre = 0, tot = 0;
+#pragma unroll
+    for (int q = 0; q < kScanThreads / 64; ++q) {
+        uint32_t s = wsum[q];
+        if (q < w) wpre += s;
+        tot += s;
+    }
+    __syncthreads();
+    total = tot;
+    return wpre + x - v;
+}
+
+// Per-tile sums.
+__global__ void __launch_bounds__(kScanThreads)
+k_scan_reduce(const uint32_t *__restrict__ in, int64_t M, uint32_t *__restrict__ sums) {
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t i = base + k;
+        if (i < M) s += in[i];
+    }
+    uint32_t tot;
+    block_exclusive(s, tot);
+    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+// Exclusive scan of each tile plus the tile's scanned offset (offsets may be
+// null for a single tile).  In-place (in == out) is allowed.
+__global__ void __launch_bounds__(kScanThreads)
+k_scan_down(const uint32_t *in, uint32_t *out, int64_t M, const uint32_t *__restrict__ offsets) {
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+    uint32_t v[kScanItems];
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t i = base + k;
+        v[k] = (i < M) ? in[i] : 0u;
+        s += v[k];
+    }
+    uint32_t tot;
+    uint32_t run = block_exclusive(s, tot) + (offsets ? offsets[blockIdx.x] : 0u);
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t i = base + k;
+        if (i < M) out[i] = run;
+        run += v[k];
+    }
+}
+
+// ------------------------------------------------------------- finish
+
+// Per box: cell_start from the scanned cell counts, order from the sorted
+// element indices, and the float offsets recomputed from the positions.
+__global__ void __launch_bounds__(256)
+k_bin_finish(const DevBox *boxes, const uint32_t *__restrict__ cellscan,
+             const uint32_t *__restrict__ vals_sorted) {
+    const DevBox &B = boxes[blockIdx.y];
+    int t = blockIdx.x * 256 + threadIdx.x;
+    if (t <= B.ncell) B.cell_start[t] = (int32_t)((int64_t)cellscan[B.cellbase + t] - B.base);
+    if (t < B.n) {
+        int64_t gi = (int64_t)vals_sorted[B.base + t] - B.base;
+        int i = (gi >= 0 && gi < B.n) ? (int)gi : 0;   // always in range for a valid sort
+        B.order[t] = i;
+        float o[3];
+        bool ok = true;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            int c;
+            double od;
+            ok &= cell_coord(B.pos[3 * (int64_t)i + a], B.kappa, B.K, c, od);
+            o[a] = (float)od;
+        }
+        if (!ok) o[0] = o[1] = o[2] = 0.0f;
+        B.off[t] = make_float4(o[0], o[1], o[2], 0.0f);
+    }
+}
+
+// ------------------------------------------------------------- host driver
+
+int64_t scan_scratch_words(int64_t M) {
+    // words needed by scan_exclusive(M): the sums of each level, recursively
+    int64_t words = 0;
+    while (M > kScanTile) {
+        int64_t nb = (M + kScanTile - 1) / kScanTile;
+        words += nb;
+        M = nb;
+    }
+    return words + 64;
+}
+
+static hipError_t scan_exclusive(uint32_t *data, int64_t M, uint32_t *scratch, hipStream_t s) {
+    if (M <= kScanTile) {
+        hipLaunchKernelGGL(k_scan_down, dim3(1), dim3(kScanThreads), 0, s, data, data, M,
+                           (const uint32_t *)nullptr);
+        return hipGetLastError();
+    }
+    int64_t nb = (M + kScanTile - 1) / kScanTile;
+    uint32_t *sums = scratch;
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, data, M, sums);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = scan_exclusive(sums, nb, scratch + nb, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kScanThreads), 0, s, data, data, M,
+                       (const uint32_t *)sums);
+    return hipGetLastError();
+}
+
+hipError_t bin_launch(const DevBox *d_boxes, int nbox, const BinPlan &p, hipStream_t s) {
+    hipError_t e;
+    const unsigned fill_blocks = (unsigned)std::min<int64_t>(4096, (p.C + 1 + 255) / 256 + 1);
+    hipLaunchKernelGGL(k_fill_u32, dim3(fill_blocks), dim3(256), 0, s, p.sc.cellcnt, p.C + 1, 0u);
+    hipLaunchKernelGGL(k_bin_zero_status, dim3((nbox + 255) / 256), dim3(256), 0, s, d_boxes, nbox);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (p.N > 0) {
+        hipLaunchKernelGGL(k_bin_keys, dim3((unsigned)((p.max_n + 255) / 256), (unsigned)nbox),
+                           dim3(256), 0, s, d_boxes, p.sc);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        int src = 0;
+        for (int pass = 0; pass < p.passes; ++pass) {
+            const int shift = pass * kRadixBits;
+            hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)p.nblk), dim3(kSortThreads), 0, s,
+                               p.sc.keys[src], p.N, shift, (int)p.nblk, p.sc.hist);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            if ((e = scan_exclusive(p.sc.hist, (int64_t)kRadix * p.nblk, p.scan_scratch, s)) !=
+                hipSuccess)
+                return e;
+            hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)p.nblk), dim3(kSortThreads), 0, s,
+                               p.sc.keys[src], p.sc.vals[src], p.sc.keys[src ^ 1],
+                               p.sc.vals[src ^ 1], p.N, shift, (int)p.nblk, p.sc.hist);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            src ^= 1;
+        }
+    }
+    if ((e = scan_exclusive(p.sc.cellcnt, p.C + 1, p.scan_scratch, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_bin_finish,
+                       dim3((unsigned)((std::max<int64_t>(p.max_n, p.max_ncell + 1) + 255) / 256),
+                            (unsigned)nbox),
+                       dim3(256), 0, s, d_boxes, (const uint32_t *)p.sc.cellcnt,
+                       (const uint32_t *)p.sc.vals[p.passes & 1]);
+    return hipGetLastError();
+}
+
+}  // namespace nf

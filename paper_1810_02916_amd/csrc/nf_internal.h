@@ -1,0 +1,97 @@
+// nf_internal.h -- device-side descriptors and helpers shared by the HIP
+// translation units of libnf.so (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nf {
+
+// Radix sort geometry: 8-bit digits, 256 threads per block, 16 keys per thread.
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 1 << kRadixBits;
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortThreads * kSortItems;   // 4096 keys per block
+
+// Scan geometry: 256 threads x 16 items per block.
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;   // 4096 values per block
+
+// Per-box descriptor as the kernels see it.  Lives in the workspace and is
+// written there by a small upload kernel (no host-to-device memcpy), so every
+// launch stays capturable in a HIP graph.
+struct DevBox {
+    // geometry
+    int32_t n;            // particles
+    int32_t K;            // cells per side
+    int32_t ncell;        // K^3
+    int32_t pad0;
+    int64_t base;         // first element of this box in the concatenated arrays
+    int64_t cellbase;     // first key of this box in the concatenated key space
+    double kappa;         // K / L (cells per length unit), double
+    float eps;            // spline radius in cell widths (eps_s * kappa)
+    float scale;          // gm * kappa^2 (accel) or gm * kappa^3 (vjp)
+    float cA, cB, cC;     // Eq. 2 in cell widths: F/r = cA + cB r + cC r^2 inside eps
+                          // (10/eps^3, -15/eps^4, 6/eps^5, rounded from double)
+    int32_t outer_newton; // 1 when eps <= 1: every pair from the outer shell of
+                          // the 5x5x5 block is at r >= 1 >= eps (Newton branch)
+    // caller buffers
+    const double *pos;    // [n][3]
+    float4 *off;          // [n] sorted offsets
+    int32_t *cell_start;  // [K^3 + 1]
+    int32_t *order;       // [n]
+    int32_t *nbad;        // [1] or null
+    float *out;           // acc or grad, [n][3], caller order
+    const float *cot;     // [n][3] cotangent (vjp), caller order
+};
+static_assert(sizeof(DevBox) % 8 == 0, "DevBox must stay 8-byte aligned");
+
+// Global (all boxes) scratch used by the binning kernels.
+struct BinScratch {
+    uint32_t *keys[2];    // [N] concatenated keys (cellbase_b + cell id)
+    uint32_t *vals[2];    // [N] concatenated element index
+    uint32_t *hist;       // [256 * nblk] digit-major block histograms
+    uint32_t *cellcnt;    // [C + 1] concatenated cell counts -> cell starts
+};
+
+// Cell of one coordinate, exactly as the method defines it: s = x * kappa
+// (one rounding), c = floor(s) mod K, o = (s - floor(s)) - 1/2.  The
+// sequence is evaluated without contraction so that host-side checks can
+// reproduce the rounded offset bit for bit.  Returns false when s is not
+// finite or |s| >= 2^62.
+__device__ __forceinline__ bool cell_coord(double x, double kappa, int K, int &c, double &o) {
+#pragma clang fp contract(off)
+    double s = x * kappa;
+    if (!(fabs(s) < 4.611686018427387904e18)) {   // also catches NaN
+        c = 0;
+        o = 0.0;
+        return false;
+    }
+    double f = floor(s);
+    double frac = s - f;
+    o = frac - 0.5;
+    long long fi = (long long)f;
+    long long r = fi % (long long)K;
+    if (r < 0) r += K;
+    c = (int)r;
+    return true;
+}
+
+// Wave-level "match any" on an 8-bit digit: mask of the active lanes whose
+// digit equals this lane's digit.
+__device__ __forceinline__ uint64_t match_digit(bool valid, uint32_t d) {
+    uint64_t m = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < kRadixBits; ++b) {
+        bool bit = (d >> b) & 1u;
+        uint64_t bb = __ballot(valid && bit);
+        m &= bit ? bb : ~bb;
+    }
+    return m;
+}
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+}  // namespace nf

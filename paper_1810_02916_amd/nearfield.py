@@ -1,0 +1,221 @@
+"""Python binding of the near-field library: argument marshalling only.
+
+Every step runs in libnf.so's HIP kernels; torch supplies device memory and
+the current stream.
+
+    b = bin_particles(pos, K, L, eps_s)        # Sec. 2.1 binning
+    a = accel(b, gm)                            # Sec. 2.1 + Eq. 2 sum
+    g = accel_vjp(b, cot, gm)                   # VJP w.r.t. positions
+    a = nearfield_accel(pos, K, L, eps_s, gm)   # autograd-enabled
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence
+
+import torch
+
+from . import _lib
+from ._lib import NF_COMPENSATED, NF_SIMPLE, NfBox
+
+__all__ = [
+    "SPLINE_PER_PLUMMER",
+    "eps_spline_from_plummer",
+    "Binned",
+    "bin_particles",
+    "bin_particles_batched",
+    "accel",
+    "accel_vjp",
+    "NearFieldAccel",
+    "nearfield_accel",
+]
+
+# Sec. 4.3: spline radius with the same minimum pairwise dynamical time as a
+# Plummer softening eps_p.
+SPLINE_PER_PLUMMER = 2.16
+
+
+def eps_spline_from_plummer(eps_p: float) -> float:
+    return SPLINE_PER_PLUMMER * float(eps_p)
+
+
+def _stream_handle(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+@dataclass
+class _BoxBuffers:
+    pos: torch.Tensor          # [n,3] float64 (kept alive)
+    K: int
+    L: float
+    eps_s: float
+    off: torch.Tensor          # [n,4] float32, sorted
+    cell_start: torch.Tensor   # [K^3+1] int32
+    order: torch.Tensor        # [n] int32
+    nbad: torch.Tensor         # [1] int32
+
+    @property
+    def n(self) -> int:
+        return int(self.pos.shape[0])
+
+    def cstruct(self) -> NfBox:
+        return NfBox(self.n, self.K, 0, self.L, self.eps_s, self.pos.data_ptr(),
+                     self.off.data_ptr(), self.cell_start.data_ptr(), self.order.data_ptr(),
+                     self.nbad.data_ptr())
+
+
+@dataclass
+class Binned:
+    """Binned boxes (one or many) plus a workspace sized for all calls."""
+    boxes: List[_BoxBuffers]
+    workspace: torch.Tensor
+    device: torch.device
+    _arr: object = field(default=None, repr=False)
+
+    def carray(self):
+        if self._arr is None:
+            arr = (NfBox * len(self.boxes))()
+            for i, b in enumerate(self.boxes):
+                arr[i] = b.cstruct()
+            self._arr = arr
+        return self._arr
+
+    @property
+    def nbox(self) -> int:
+        return len(self.boxes)
+
+    def nbad(self) -> List[int]:
+        return [int(b.nbad.item()) for b in self.boxes]
+
+
+def _prep_pos(pos: torch.Tensor) -> torch.Tensor:
+    if not isinstance(pos, torch.Tensor) or not pos.is_cuda:
+        raise ValueError("positions must be a CUDA (HIP) tensor")
+    if pos.dim() != 2 or pos.shape[1] != 3:
+        raise ValueError("positions must have shape (n, 3)")
+    return pos.detach().to(torch.float64).contiguous()
+
+
+def _alloc_box(pos: torch.Tensor, K: int, L: float, eps_s: float) -> _BoxBuffers:
+    dev = pos.device
+    n = pos.shape[0]
+    K = int(K)
+    if K < 5:
+        raise ValueError("K must be >= 5")
+    return _BoxBuffers(
+        pos=pos, K=K, L=float(L), eps_s=float(eps_s),
+        off=torch.empty((n, 4), dtype=torch.float32, device=dev),
+        cell_start=torch.empty(K ** 3 + 1, dtype=torch.int32, device=dev),
+        order=torch.empty(n, dtype=torch.int32, device=dev),
+        nbad=torch.zeros(1, dtype=torch.int32, device=dev),
+    )
+
+
+def bin_particles_batched(positions: Sequence[torch.Tensor], Ks: Sequence[int],
+                          Ls: Sequence[float], eps: Sequence[float]) -> Binned:
+    """Bin several boxes in one call (one radix sort over all of them)."""
+    lib = _lib.load()
+    if not (len(positions) == len(Ks) == len(Ls) == len(eps)) or len(positions) == 0:
+        raise ValueError("positions, Ks, Ls and eps must be non-empty and of equal length")
+    ps = [_prep_pos(p) for p in positions]
+    dev = ps[0].device
+    if any(p.device != dev for p in ps):
+        raise ValueError("all boxes must live on one device")
+    boxes = [_alloc_box(p, K, L, e) for p, K, L, e in zip(ps, Ks, Ls, eps)]
+    arr = (NfBox * len(boxes))()
+    for i, b in enumerate(boxes):
+        arr[i] = b.cstruct()
+    nbytes = lib.nf_workspace_bytes(len(boxes), arr, 0)
+    if nbytes == 0:
+        _lib.check(_lib.NF_EINVAL)
+    ws = torch.empty(int(nbytes), dtype=torch.uint8, device=dev)
+    with torch.cuda.device(dev):
+        rc = lib.nf_bin_particles(len(boxes), arr, ctypes.c_void_p(ws.data_ptr()), int(nbytes),
+                                  _stream_handle(dev))
+    _lib.check(rc)
+    out = Binned(boxes=boxes, workspace=ws, device=dev)
+    out._arr = arr
+    return out
+
+
+def bin_particles(pos: torch.Tensor, K: int, L: float, eps_s: float) -> Binned:
+    """Bin one box: cell offsets (FP64 -> FP32) and a stable sort by cell."""
+    return bin_particles_batched([pos], [K], [L], [eps_s])
+
+
+def _flags(compensated: bool, simple: bool) -> int:
+    return (NF_COMPENSATED if compensated else 0) | (NF_SIMPLE if simple else 0)
+
+
+def _ptr_array(tensors: Sequence[torch.Tensor]):
+    arr = (ctypes.c_void_p * len(tensors))()
+    for i, t in enumerate(tensors):
+        arr[i] = t.data_ptr()
+    return arr
+
+
+def accel(b: Binned, gm: float = 1.0, *, compensated: bool = False, simple: bool = False,
+          out: Optional[List[torch.Tensor]] = None):
+    """Near-field accelerations, float32 [n,3] in input order (a list for
+    several boxes)."""
+    lib = _lib.load()
+    if out is None:
+        out = [torch.empty((bx.n, 3), dtype=torch.float32, device=b.device) for bx in b.boxes]
+    ptrs = _ptr_array(out)
+    with torch.cuda.device(b.device):
+        rc = lib.nf_accel(b.nbox, b.carray(), float(gm), _flags(compensated, simple), ptrs,
+                          ctypes.c_void_p(b.workspace.data_ptr()), b.workspace.numel(),
+                          _stream_handle(b.device))
+    _lib.check(rc)
+    return out[0] if b.nbox == 1 else out
+
+
+def accel_vjp(b: Binned, cot, gm: float = 1.0, *, compensated: bool = False,
+              simple: bool = False):
+    """Vector-Jacobian product of the accelerations w.r.t. positions
+    (cell assignment held fixed); float32 [n,3] per box."""
+    lib = _lib.load()
+    cots = [cot] if isinstance(cot, torch.Tensor) else list(cot)
+    if len(cots) != b.nbox:
+        raise ValueError("one cotangent per box is required")
+    cots = [c.detach().to(device=b.device, dtype=torch.float32).contiguous() for c in cots]
+    for c, bx in zip(cots, b.boxes):
+        if tuple(c.shape) != (bx.n, 3):
+            raise ValueError("cotangent must have shape (n, 3)")
+    grads = [torch.empty((bx.n, 3), dtype=torch.float32, device=b.device) for bx in b.boxes]
+    with torch.cuda.device(b.device):
+        rc = lib.nf_accel_vjp(b.nbox, b.carray(), float(gm), _flags(compensated, simple),
+                              _ptr_array(cots), _ptr_array(grads),
+                              ctypes.c_void_p(b.workspace.data_ptr()), b.workspace.numel(),
+                              _stream_handle(b.device))
+    _lib.check(rc)
+    return grads[0] if b.nbox == 1 else grads
+
+
+class NearFieldAccel(torch.autograd.Function):
+    """acc = near-field acceleration of positions ``pos`` (float64 [n,3]).
+
+    The backward pass is the hand-written VJP kernel with the binning of the
+    forward pass held fixed."""
+
+    @staticmethod
+    def forward(ctx, pos, K, L, eps_s, gm, compensated):
+        b = bin_particles(pos, K, L, eps_s)
+        a = accel(b, gm, compensated=compensated)
+        ctx.binned = b
+        ctx.gm = gm
+        ctx.compensated = compensated
+        ctx.pos_dtype = pos.dtype
+        return a
+
+    @staticmethod
+    @torch.autograd.function.once_differentiable
+    def backward(ctx, grad_acc):
+        g = accel_vjp(ctx.binned, grad_acc, ctx.gm, compensated=ctx.compensated)
+        return g.to(ctx.pos_dtype), None, None, None, None, None
+
+
+def nearfield_accel(pos: torch.Tensor, K: int, L: float, eps_s: float, gm: float = 1.0,
+                    compensated: bool = False) -> torch.Tensor:
+    return NearFieldAccel.apply(pos, K, L, eps_s, gm, compensated)

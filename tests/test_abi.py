@@ -1,0 +1,121 @@
+"""Host-side checks of libnf.so (no GPU needed): the library loads, exports
+every function include/nf.h declares, lays out nf_box as the header does,
+and rejects bad arguments before touching a device."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "nf.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1810_02916_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1810_02916_amd import build
+        build.build()
+    return _lib
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(nf_[a-z_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared()
+    assert set(names) == set(lib.EXPORTED)
+    out = subprocess.run(["nm", "-D", "--defined-only", lib.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (nf_[a-z_]+)\b", out))
+    for n in names:
+        assert n in exported, n
+    handle = ctypes.CDLL(lib.LIB_PATH)
+    for n in names:
+        getattr(handle, n)
+
+
+def test_version_and_strerror(lib):
+    L = lib.load()
+    ver = int(re.search(r"#define NF_ABI_VERSION (\d+)", open(HEADER).read()).group(1))
+    assert L.nf_version() == ver
+    for code in range(5):
+        assert L.nf_strerror(code)
+    assert L.nf_strerror(99) == b"unknown status"
+
+
+def test_struct_layout_matches_header(lib, tmp_path):
+    prog = tmp_path / "layout.c"
+    prog.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "nf.h"\n'
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\","
+        "sizeof(nf_box), offsetof(nf_box,n), offsetof(nf_box,K), offsetof(nf_box,reserved),"
+        "offsetof(nf_box,L), offsetof(nf_box,eps_s), offsetof(nf_box,pos), offsetof(nf_box,off),"
+        "offsetof(nf_box,cell_start), offsetof(nf_box,order), offsetof(nf_box,nbad));return 0;}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)],
+                   check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    B = lib.NfBox
+    want = [ctypes.sizeof(B)] + [getattr(B, f).offset for f in
+                                 ("n", "K", "reserved", "L", "eps_s", "pos", "off", "cell_start",
+                                  "order", "nbad")]
+    assert got == want
+
+
+def _box(lib, n=10, K=8, L=1.0, eps=0.01, ptr=0x1000):
+    return lib.NfBox(n, K, 0, L, eps, ptr, ptr, ptr, ptr, None)
+
+
+def test_workspace_bytes_and_validation(lib):
+    L = lib.load()
+    arr = (lib.NfBox * 2)(_box(lib, 1000, 8), _box(lib, 0, 5))
+    assert L.nf_workspace_bytes(2, arr, 0) > 0
+    bad = [
+        _box(lib, -1),
+        _box(lib, K=4),
+        _box(lib, L=0.0),
+        _box(lib, L=float("inf")),
+        _box(lib, eps=0.0),
+        _box(lib, eps=float("nan")),
+        lib.NfBox(10, 8, 0, 1.0, 0.01, 0x1000, 0, 0x1000, 0x1000, None),   # off NULL
+        lib.NfBox(0, 8, 0, 1.0, 0.01, 0, 0, 0, 0, None),                    # cell_start NULL
+    ]
+    for b in bad:
+        one = (lib.NfBox * 1)(b)
+        assert L.nf_workspace_bytes(1, one, 0) == 0
+        assert lib.last_error()
+    big = (lib.NfBox * 1)(_box(lib, 10, K=1300))
+    assert L.nf_workspace_bytes(1, big, 0) == 0
+    assert L.nf_workspace_bytes(0, arr, 0) == 0
+
+
+def test_calls_reject_bad_arguments_without_a_device(lib):
+    L = lib.load()
+    one = (lib.NfBox * 1)(_box(lib, 10, K=4))
+    ws = ctypes.c_void_p(0x100000)
+    assert L.nf_bin_particles(1, one, ws, 1 << 20, None) == lib.NF_EINVAL
+    good = (lib.NfBox * 1)(_box(lib, 10))
+    assert L.nf_bin_particles(1, good, None, 1 << 20, None) == lib.NF_EWORKSPACE
+    assert L.nf_bin_particles(1, good, ws, 16, None) == lib.NF_EWORKSPACE
+    assert L.nf_bin_particles(1, good, ctypes.c_void_p(0x100001), 1 << 30, None) == lib.NF_EWORKSPACE
+    outs = (ctypes.c_void_p * 1)(0x2000)
+    assert L.nf_accel(1, good, 1.0, 1 << 7, outs, ws, 1 << 20, None) == lib.NF_EINVAL
+    assert L.nf_accel(1, good, float("nan"), 0, outs, ws, 1 << 20, None) == lib.NF_EINVAL
+    nulls = (ctypes.c_void_p * 1)(None)
+    assert L.nf_accel(1, good, 1.0, 0, nulls, ws, 1 << 20, None) == lib.NF_EINVAL
+    assert L.nf_accel_vjp(1, good, 1.0, 0, None, outs, ws, 1 << 20, None) == lib.NF_EINVAL
+    assert "cotangent" in lib.last_error()
+
+
+def test_python_binding_raises_without_gpu_tensors(lib):
+    import torch
+    from paper_1810_02916_amd import nearfield
+    with pytest.raises(ValueError):
+        nearfield.bin_particles(torch.zeros((4, 3), dtype=torch.float64), 8, 1.0, 0.01)

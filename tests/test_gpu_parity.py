@@ -1,0 +1,229 @@
+"""GPU parity of the HIP path against the FP64 oracle.
+
+Tolerances (normalised rms error against the FP64 oracle on exact offsets):
+plain FP32 accumulation <= 1e-5, compensated (Kahan) accumulation <= 1e-6.
+Binning is bit-exact: cell_start and order equal the oracle's, and every
+offset equals the oracle's double offset rounded to float.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1810_02916_amd import nearfield as nfp
+from paper_1810_02916_amd.synth import (WORKLOADS, batched_specs, clustered_box,
+                                        gaussian_cotangent, make_box, uniform_box)
+from tests.errstats import err_stats
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+TOL_PLAIN = 1e-5
+TOL_COMP = 1e-6
+
+
+def _gpu(pos):
+    return torch.from_numpy(np.ascontiguousarray(pos)).to(DEV)
+
+
+def _bin_check(pos, K, L, eps=0.01):
+    b = nfp.bin_particles(_gpu(pos), K, L, eps)
+    torch.cuda.synchronize()
+    cs, order, off = oracle.bin_particles(pos, K, L)
+    bx = b.boxes[0]
+    np.testing.assert_array_equal(bx.cell_start.cpu().numpy(), cs)
+    np.testing.assert_array_equal(bx.order.cpu().numpy(), order)
+    got = bx.off.cpu().numpy()
+    assert got.view(np.uint32).tobytes() == off.view(np.uint32).tobytes(), "offsets differ bitwise"
+    return b
+
+
+# ------------------------------------------------------------------ binning
+
+@pytest.mark.parametrize("name", ["uniform32k", "clustered262k"])
+def test_bin_bit_exact(name):
+    sp = WORKLOADS[name]
+    print(f"[bin] {name}", flush=True)
+    _bin_check(make_box(sp), sp.K, sp.L)
+
+
+def test_bin_faces_and_wrapping():
+    """Particles on cell faces, at x = 0 and x = L, slightly negative, and
+    many box lengths away all bin exactly as the oracle does."""
+    K, L = 7, 3.0
+    h = L / K
+    rng = np.random.default_rng(7)
+    faces = np.array([[i * h, j * h, k * h] for i in range(K + 1) for j in (0, 3) for k in (1, K)],
+                     dtype=np.float64)
+    pos = np.concatenate([
+        faces,
+        np.array([[0.0, 0.0, 0.0], [L, L, L], [-1e-17, -1e-300, -0.0], [L - 1e-16, 1e-16, 0.5 * h],
+                  [-7.25 * L, 13.5 * L, 1e6 * L + 0.1], [-h / 2, h / 2, -h]]),
+        rng.uniform(-2 * L, 3 * L, size=(500, 3)),
+    ])
+    _bin_check(pos, K, L)
+
+
+def test_bin_ragged_and_empty_cells():
+    """Tiles with a ragged tail: n not a multiple of the 4096-key sort tile,
+    many empty cells, one very dense cell."""
+    rng = np.random.default_rng(11)
+    K, L = 24, 1.0
+    dense = 0.5 + 0.001 * rng.random((5001, 3))
+    sparse = rng.random((777, 3))
+    pos = np.concatenate([dense, sparse])[rng.permutation(5778)]
+    _bin_check(pos, K, L)
+
+
+def test_bin_empty_box_and_nonfinite():
+    K, L = 5, 1.0
+    b = nfp.bin_particles(torch.empty((0, 3), dtype=torch.float64, device=DEV), K, L, 0.01)
+    torch.cuda.synchronize()
+    assert (b.boxes[0].cell_start.cpu().numpy() == 0).all()
+    pos = np.array([[0.1, 0.2, 0.3], [np.nan, 0.5, 0.5], [0.7, np.inf, 0.1], [0.4, 0.4, 4e62]])
+    b = nfp.bin_particles(_gpu(pos), K, L, 0.01)
+    torch.cuda.synchronize()
+    assert b.nbad() == [3]
+    order = b.boxes[0].order.cpu().numpy()
+    assert sorted(order.tolist()) == [0, 1, 2, 3]
+
+
+def test_bin_batched_matches_single():
+    specs = batched_specs(4, seed=5, lo=4000, hi=9000)
+    poss = [make_box(s) for s in specs]
+    bb = nfp.bin_particles_batched([_gpu(p) for p in poss], [s.K for s in specs],
+                                   [s.L for s in specs], [s.eps_s for s in specs])
+    torch.cuda.synchronize()
+    for p, s, bx in zip(poss, specs, bb.boxes):
+        cs, order, off = oracle.bin_particles(p, s.K, s.L)
+        np.testing.assert_array_equal(bx.cell_start.cpu().numpy(), cs)
+        np.testing.assert_array_equal(bx.order.cpu().numpy(), order)
+        assert bx.off.cpu().numpy().tobytes() == off.tobytes()
+
+
+# ------------------------------------------------------------------ accel
+
+def _accel(pos, K, L, eps, gm=1.0, **kw):
+    b = nfp.bin_particles(_gpu(pos), K, L, eps)
+    a = nfp.accel(b, gm, **kw)
+    torch.cuda.synchronize()
+    return a.cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("simple", [False, True])
+@pytest.mark.parametrize("compensated", [False, True])
+@pytest.mark.parametrize("name", ["uniform32k", "clustered262k"])
+def test_accel_parity(name, compensated, simple):
+    sp = WORKLOADS[name]
+    pos = make_box(sp)
+    print(f"[accel] {name} comp={compensated} simple={simple}", flush=True)
+    got = _accel(pos, sp.K, sp.L, sp.eps_s, compensated=compensated, simple=simple)
+    ref = oracle.accel(pos, sp.K, sp.L, sp.eps_s)
+    st = err_stats(got, ref)
+    print(name, compensated, simple, st)
+    assert st["rms"] <= (TOL_COMP if compensated else TOL_PLAIN), st
+
+
+def test_accel_clustered2m_sampled():
+    """Full-size clustered box (128^3 particles, 64^3 cells) in the launch
+    configuration of the benchmark, checked on sampled sinks: 4096 random
+    sinks plus every sink of the 4 densest cells."""
+    sp = WORKLOADS["clustered2m"]
+    pos = make_box(sp)
+    b = nfp.bin_particles(_gpu(pos), sp.K, sp.L, sp.eps_s)
+    a_plain = nfp.accel(b, 1.0).cpu().numpy()
+    a_comp = nfp.accel(b, 1.0, compensated=True).cpu().numpy()
+    cs = b.boxes[0].cell_start.cpu().numpy()
+    order = b.boxes[0].order.cpu().numpy()
+    counts = np.diff(cs)
+    dense = np.argsort(counts)[-4:]
+    rng = np.random.default_rng(3)
+    sinks = np.unique(np.concatenate(
+        [rng.choice(pos.shape[0], 4096, replace=False)] +
+        [order[cs[c]:cs[c + 1]] for c in dense]))
+    ref = oracle.accel(pos, sp.K, sp.L, sp.eps_s, sinks=sinks)
+    sp_ = err_stats(a_plain[sinks], ref)
+    sc_ = err_stats(a_comp[sinks], ref)
+    print("clustered2m plain", sp_, "comp", sc_)
+    assert sp_["rms"] <= TOL_PLAIN
+    assert sc_["rms"] <= TOL_COMP
+
+
+def test_accel_deterministic():
+    sp = WORKLOADS["clustered262k"]
+    pos = make_box(sp)
+    b = nfp.bin_particles(_gpu(pos), sp.K, sp.L, sp.eps_s)
+    r = [nfp.accel(b, 1.0, compensated=c).cpu().numpy() for c in (False, True, False, True)]
+    assert r[0].tobytes() == r[2].tobytes()
+    assert r[1].tobytes() == r[3].tobytes()
+
+
+def test_accel_two_body_and_coincident():
+    """Two particles inside, at and outside eps, across a periodic face, and a
+    coincident pair (zero force)."""
+    K, L, gm = 8, 1.0, 2.5
+    eps = 0.05
+    cases = [
+        [[0.30, 0.30, 0.30], [0.32, 0.30, 0.30]],   # inside eps
+        [[0.30, 0.30, 0.30], [0.30, 0.35, 0.30]],   # at eps
+        [[0.30, 0.30, 0.30], [0.30, 0.30, 0.45]],   # outside
+        [[0.01, 0.50, 0.50], [0.99, 0.50, 0.50]],   # across the face x = 0
+        [[0.60, 0.60, 0.60], [0.60, 0.60, 0.60]],   # coincident
+    ]
+    for pos in cases:
+        pos = np.array(pos)
+        got = _accel(pos, K, L, eps, gm, compensated=True)
+        ref = oracle.accel(pos, K, L, eps, gm)
+        scale = max(np.abs(ref).max(), 1e-30)
+        assert np.abs(got - ref).max() <= 2e-6 * scale, (pos, got, ref)
+
+
+def test_accel_K5_whole_box():
+    """K = 5: the 5x5x5 block is the whole box, every pair interacts once."""
+    pos = uniform_box(1500, 2.0, 21)
+    got = _accel(pos, 5, 2.0, 0.05, compensated=True)
+    ref = oracle.brute_accel(pos, 5, 2.0, 0.05)
+    assert err_stats(got, ref)["rms"] <= TOL_COMP
+
+
+def test_accel_batched_bitwise_equals_single():
+    specs = batched_specs(5, seed=9, lo=3000, hi=20000)
+    poss = [make_box(s) for s in specs]
+    bb = nfp.bin_particles_batched([_gpu(p) for p in poss], [s.K for s in specs],
+                                   [s.L for s in specs], [s.eps_s for s in specs])
+    for comp in (False, True):
+        batched = [a.cpu().numpy() for a in nfp.accel(bb, 1.0, compensated=comp)]
+        for p, s, ab in zip(poss, specs, batched):
+            single = _accel(p, s.K, s.L, s.eps_s, compensated=comp).astype(np.float32)
+            assert single.tobytes() == ab.tobytes()
+            ref = oracle.accel(p, s.K, s.L, s.eps_s)
+            assert err_stats(ab, ref)["rms"] <= (TOL_COMP if comp else TOL_PLAIN)
+
+
+# ------------------------------------------------------------------ vjp
+
+@pytest.mark.parametrize("compensated", [False, True])
+def test_vjp_matches_oracle(compensated):
+    sp = WORKLOADS["clustered262k"]
+    pos = make_box(sp)
+    v = gaussian_cotangent(sp.n, 1815 * 10 + 2)
+    b = nfp.bin_particles(_gpu(pos), sp.K, sp.L, sp.eps_s)
+    g = nfp.accel_vjp(b, torch.from_numpy(v.astype(np.float32)).to(DEV), 1.0,
+                      compensated=compensated).cpu().numpy()
+    # the cotangent the kernel sees is float32; feed the oracle the same values
+    ref = oracle.jvp(pos, sp.K, sp.L, sp.eps_s, v.astype(np.float32).astype(np.float64))
+    st = err_stats(g, ref)
+    print("vjp", compensated, st)
+    assert st["rms"] <= (TOL_COMP if compensated else TOL_PLAIN), st
+
+
+def test_autograd_backward_is_vjp():
+    sp = WORKLOADS["clustered262k"]
+    pos = _gpu(make_box(sp)).requires_grad_(True)
+    a = nfp.nearfield_accel(pos, sp.K, sp.L, sp.eps_s, 1.0)
+    v = torch.from_numpy(gaussian_cotangent(sp.n, 77).astype(np.float32)).to(DEV)
+    (a * v).sum().backward()
+    b = nfp.bin_particles(pos.detach(), sp.K, sp.L, sp.eps_s)
+    g = nfp.accel_vjp(b, v, 1.0)
+    assert pos.grad.dtype == torch.float64
+    assert torch.equal(pos.grad.float(), g)
