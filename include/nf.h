@@ -84,8 +84,9 @@ enum {
 /*
  * One periodic box.  Layouts:
  *   pos         [n][3] double, caller (input) order.  Read by nf_bin_particles.
- *   off         [n][4] float, cell-sorted: (ox, oy, oz, 0), the offsets of
- *               Sec. 2.1 in cell widths, each in [-1/2, 1/2].
+ *   off         [n][4] float, cell-sorted: (ox, oy, oz, cz): the offsets of
+ *               Sec. 2.1 in cell widths, each in [-1/2, 1/2], and the
+ *               particle's z cell index cz (an integer stored as float).
  *               Written by nf_bin_particles, read by nf_accel / nf_accel_vjp.
  *   cell_start  [K^3 + 1] int32: sorted slots of cell c are
  *               cell_start[c] .. cell_start[c+1]-1; cell_start[K^3] = n.

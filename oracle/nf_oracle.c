@@ -95,8 +95,9 @@ int oracle_cells(int64_t n, const double *pos, int32_t K, double L,
  * Binning: stable counting sort of particles by linear cell id.
  *   cell_start[K^3 + 1]  first sorted slot of each cell (cell_start[K^3] = n)
  *   order[n]             input index of each sorted slot
- *   off32[n][4]          (ox, oy, oz, 0) of each sorted slot, each offset
- *                        rounded to float with round-to-nearest-even
+ *   off32[n][4]          (ox, oy, oz, cz) of each sorted slot: each offset
+ *                        rounded to float with round-to-nearest-even, and
+ *                        the z cell index as a float
  */
 int oracle_bin(int64_t n, const double *pos, int32_t K, double L,
                int32_t *cell_start, int32_t *order, float *off32) {
@@ -129,7 +130,7 @@ int oracle_bin(int64_t n, const double *pos, int32_t K, double L,
         off32[4 * slot + 0] = (float)off[3 * i + 0];
         off32[4 * slot + 1] = (float)off[3 * i + 1];
         off32[4 * slot + 2] = (float)off[3 * i + 2];
-        off32[4 * slot + 3] = 0.0f;
+        off32[4 * slot + 3] = (float)cell[3 * i + 2];
     }
     free(cell); free(off); free(count);
     return OR_OK;

@@ -210,10 +210,18 @@ hipError_t accel_launch(const DevBox *d_boxes, int nbox, const ForcePlan &p, hip
     return hipGetLastError();
 }
 
-hipError_t vjp_launch(const DevBox *d_boxes, int nbox, const ForcePlan &p, hipStream_t s) {
+hipError_t gather_cot_launch(const DevBox *d_boxes, int nbox, const ForcePlan &p, hipStream_t s) {
     if (p.max_n == 0) return hipSuccess;
     dim3 grid((unsigned)((p.max_n + 255) / 256), (unsigned)nbox);
     hipLaunchKernelGGL(k_gather_cot, grid, dim3(256), 0, s, d_boxes, p.cot_sorted);
+    return hipGetLastError();
+}
+
+hipError_t vjp_launch(const DevBox *d_boxes, int nbox, const ForcePlan &p, hipStream_t s) {
+    if (p.max_n == 0) return hipSuccess;
+    dim3 grid((unsigned)((p.max_n + 255) / 256), (unsigned)nbox);
+    hipError_t e = gather_cot_launch(d_boxes, nbox, p, s);
+    if (e != hipSuccess) return e;
     if (p.compensated)
         hipLaunchKernelGGL(k_vjp_simple<true>, grid, dim3(256), 0, s, d_boxes,
                            (const float4 *)p.cot_sorted);

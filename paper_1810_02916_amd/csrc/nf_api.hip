@@ -48,6 +48,7 @@ hipError_t upload(const void *src, size_t nbytes, void *dst, hipStream_t s) {
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+
 // Device architecture check, cached per device.
 std::mutex g_dev_mu;
 std::vector<int> g_dev_ok;   // -1 unknown, 0 no, 1 yes
@@ -86,7 +87,8 @@ struct Layout {
     size_t table_off = 0, table_bytes = 0;
     size_t keys_off[2] = {0, 0}, vals_off[2] = {0, 0};
     size_t hist_off = 0, cellcnt_off = 0, scan_off = 0;
-    size_t cot_off = 0;
+    size_t cot_off = 0, hcnt_off = 0, lcnt_off = 0, items_off = 0, counter_off = 0, fscan_off = 0;
+    int64_t max_items = 0;
     size_t total = 0;
     int64_t nblk = 0;
     int passes = 0;
@@ -154,6 +156,18 @@ int validate(int nbox, const nf_box *boxes, Layout &L) {
     o = scratch0;
     L.cot_off = o;
     o = align_up(o + 16 * (size_t)L.N, 256);
+    L.hcnt_off = o;
+    o = align_up(o + 4 * (size_t)(L.C + 1), 256);
+    L.lcnt_off = o;
+    o = align_up(o + 4 * (size_t)(L.C + 1), 256);
+    // items: one per non-empty cell plus one per 64 extra sinks of dense cells
+    L.max_items = L.N / 64 + L.C + 16;
+    L.items_off = o;
+    o = align_up(o + sizeof(Item) * (size_t)L.max_items, 256);
+    L.counter_off = o;
+    o = align_up(o + 4, 256);
+    L.fscan_off = o;
+    o = align_up(o + 4 * (size_t)scan_scratch_words(L.C + 1), 256);
     L.total = std::max(bin_end, o);
     return NF_OK;
 }
@@ -301,7 +315,22 @@ static int force_common(int nbox, const nf_box *boxes, double gm, uint32_t flags
     p.compensated = (flags & NF_COMPENSATED) != 0;
     p.simple = (flags & NF_SIMPLE) != 0;
     p.cot_sorted = reinterpret_cast<float4 *>(w + L.cot_off);
-    e = vjp ? vjp_launch(d_tab, nbox, p, s) : accel_launch(d_tab, nbox, p, s);
+    if (p.simple || L.N == 0) {
+        e = vjp ? vjp_launch(d_tab, nbox, p, s) : accel_launch(d_tab, nbox, p, s);
+    } else {
+        TilePlan tp;
+        tp.TG = L.C;
+        tp.max_cells = L.max_ncell;
+        tp.hcnt = reinterpret_cast<uint32_t *>(w + L.hcnt_off);
+        tp.lcnt = reinterpret_cast<uint32_t *>(w + L.lcnt_off);
+        tp.items = reinterpret_cast<Item *>(w + L.items_off);
+        tp.counter = reinterpret_cast<uint32_t *>(w + L.counter_off);
+        tp.scan_scratch = reinterpret_cast<uint32_t *>(w + L.fscan_off);
+        e = vjp ? gather_cot_launch(d_tab, nbox, p, s) : hipSuccess;
+        if (e == hipSuccess) e = plan_launch(d_tab, nbox, tp, s);
+        if (e == hipSuccess)
+            e = tile_launch(d_tab, vjp ? 1 : 0, p.compensated, tp, p.cot_sorted, s);
+    }
     if (e != hipSuccess) return fail(NF_EHIP, std::string("force launch: ") + hipGetErrorString(e));
     g_last_error.clear();
     return NF_OK;

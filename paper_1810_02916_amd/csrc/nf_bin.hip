@@ -214,16 +214,19 @@ k_bin_finish(const DevBox *boxes, const uint32_t *__restrict__ cellscan,
         int i = (gi >= 0 && gi < B.n) ? (int)gi : 0;   // always in range for a valid sort
         B.order[t] = i;
         float o[3];
+        int c[3];
         bool ok = true;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            int c;
             double od;
-            ok &= cell_coord(B.pos[3 * (int64_t)i + a], B.kappa, B.K, c, od);
+            ok &= cell_coord(B.pos[3 * (int64_t)i + a], B.kappa, B.K, c[a], od);
             o[a] = (float)od;
         }
-        if (!ok) o[0] = o[1] = o[2] = 0.0f;
-        B.off[t] = make_float4(o[0], o[1], o[2], 0.0f);
+        if (!ok) {
+            o[0] = o[1] = o[2] = 0.0f;
+            c[2] = 0;
+        }
+        B.off[t] = make_float4(o[0], o[1], o[2], (float)c[2]);
     }
 }
 
@@ -240,7 +243,7 @@ int64_t scan_scratch_words(int64_t M) {
     return words + 64;
 }
 
-static hipError_t scan_exclusive(uint32_t *data, int64_t M, uint32_t *scratch, hipStream_t s) {
+hipError_t scan_exclusive(uint32_t *data, int64_t M, uint32_t *scratch, hipStream_t s) {
     if (M <= kScanTile) {
         hipLaunchKernelGGL(k_scan_down, dim3(1), dim3(kScanThreads), 0, s, data, data, M,
                            (const uint32_t *)nullptr);
@@ -255,6 +258,13 @@ static hipError_t scan_exclusive(uint32_t *data, int64_t M, uint32_t *scratch, h
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kScanThreads), 0, s, data, data, M,
                        (const uint32_t *)sums);
+    return hipGetLastError();
+}
+
+hipError_t fill_u32(uint32_t *p, int64_t count, uint32_t value, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    const unsigned blocks = (unsigned)std::min<int64_t>(4096, (count + 255) / 256);
+    hipLaunchKernelGGL(k_fill_u32, dim3(blocks), dim3(256), 0, s, p, count, value);
     return hipGetLastError();
 }
 

