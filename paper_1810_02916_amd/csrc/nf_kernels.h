@@ -31,14 +31,18 @@ hipError_t bin_launch(const DevBox *d_boxes, int nbox, const BinPlan &p, hipStre
 
 // Planner + tile kernels (nf_tile.hip).
 struct TilePlan {
-    int64_t TG = 0;           // cells over all boxes (planning is per cell)
-    int64_t max_cells = 0;    // largest per-box cell count
-    uint32_t *hcnt = nullptr; // [TG + 1] dense-chunk items per cell -> scan
-    uint32_t *lcnt = nullptr; // [TG + 1] whole-cell items per cell -> scan
-    Item *items = nullptr;    // [max items]
-    uint32_t *counter = nullptr;
+    int64_t TG = 0;              // cells over all boxes (planning is per cell)
+    int64_t max_cells = 0;       // largest per-box cell count
+    uint32_t *lcnt = nullptr;    // [TG + 1] light items per cell -> exclusive scan
+    uint32_t *bucket_cnt = nullptr;   // [plan_buckets()] dense items per cost bucket
+    uint32_t *bucket_off = nullptr;   // [plan_buckets()] first dense item of each bucket
+    uint32_t *totals = nullptr;  // [2] dense and light item counts
+    Item *dense = nullptr;       // dense items, heaviest first
+    Item *light = nullptr;       // light items, cell order
+    uint32_t *counter = nullptr; // [2] queue counters
     uint32_t *scan_scratch = nullptr;
 };
+int plan_buckets();
 hipError_t plan_launch(const DevBox *d_boxes, int nbox, const TilePlan &tp, hipStream_t s);
 // mode 0: accelerations, 1: VJP (cot = cotangents in sorted order)
 hipError_t tile_launch(const DevBox *d_boxes, int mode, bool compensated, const TilePlan &tp,

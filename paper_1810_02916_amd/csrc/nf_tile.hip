@@ -1,24 +1,27 @@
 // nf_tile.hip -- tiled near-field kernels for gfx950: a device-side planner
-// that cuts the cell grid into work items, and a persistent one-wave-per-
-// workgroup kernel that stages each item's sources in LDS and sums the pair
-// forces of Eq. 2 (Sec. 4.3) over the 5x5x5 cell block of Sec. 2.1.
+// that cuts the cell grid into work items, and two persistent one-wave-per-
+// workgroup kernels that sum the pair forces of Eq. 2 (Sec. 4.3) over the
+// 5x5x5 cell block of Sec. 2.1.
 //
-// Work items (one wave each): all sinks of a cell with at most 64
-// particles, or 64 sinks of a denser cell.  Dense items are queued first; a
-// global counter hands items to waves, and every wave leaves once the queue
-// is empty.
-//
-// Staging: the item's 125 source cells are copied into LDS in the sink
-// cell's own frame, (o_x + dx, o_y + dy, o_z + dz) for a source cell at
-// (dx, dy, dz), the 27 cells with |d| <= 1 first, then the 98 outer cells.
-// Sources of the sink's own cell are copied unchanged, so the closest pairs
-// are formed from the exact float offsets.  Outer cells are at r >= 1 and
-// take the Newton branch directly when eps <= 1.  A union larger than the
-// LDS buffer is streamed through it in windows.
-//
-// Lanes: a unit of g <= 64 sinks is spread over the wave as (sink a, source
-// slice b), lane = a + g b, P = 64 / g slices; slices are summed at the end
-// in a fixed order.
+// Work items (one wave each):
+//   * dense  -- 64 sinks (or the remainder) of a cell holding more than 32
+//               particles.  One sink per lane; every lane needs the same
+//               source at the same time, so sources are read from the
+//               cell-sorted array with scalar loads and enter the arithmetic
+//               as SGPR operands, and the sink is shifted into each source
+//               cell's frame.  No LDS, so many waves fit on a CU and hide the
+//               load latency.  Items run heaviest neighbourhood first.
+//   * light  -- all sinks of a cell holding 1..32 particles.  The 125 source
+//               cells are staged in LDS in the sink cell's own frame,
+//               (o_x + dx, o_y + dy, o_z + dz), the 27 cells with |d| <= 1
+//               first, then the 98 outer cells, so the sum is two contiguous
+//               segments; the g sinks are spread over the wave as (sink a,
+//               source slice b), lane = a + g b, P = 64 / g slices, summed at
+//               the end in a fixed order.
+// In both paths a source of the sink's own cell is used unshifted, so the
+// closest pairs are formed from the exact float offsets, and a cell of the
+// outer shell of the block (some |d| = 2) is at r >= 1 and takes the Newton
+// branch directly when eps <= 1.
 #include "nf_internal.h"
 #include "nf_kernels.h"
 
@@ -26,44 +29,97 @@ namespace nf {
 
 namespace {
 
-constexpr int kUnit = 64;      // sinks per unit (one wave)
-constexpr int kRows = 25;      // (dx, dy) rows of the 5x5x5 block
+constexpr int kUnit = 64;            // sinks per wave
+constexpr int kDenseMin = 33;        // cells with more particles go to the dense path
+constexpr int kRows = 25;            // (dx, dy) rows of the 5x5x5 block
 constexpr float kTinyT = 1.0e-30f;   // floor on r^2: a coincident pair gives 0
-constexpr int kFlush = 32;     // compensated mode: plain partials of <= 32 terms
+constexpr int kFlush = 32;           // compensated mode: plain partials of <= 32 terms
 
 __device__ __forceinline__ int wrapk(int c, int K) { return c < 0 ? c + K : (c >= K ? c - K : c); }
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
 // ------------------------------------------------------------------ planner
 
-// Items of one cell: ceil(n / 64) chunks when n > 64 (dense), one item when
-// 1 <= n <= 64, none when empty.
-__global__ void __launch_bounds__(256)
-k_plan_count(const DevBox *boxes, uint32_t *hcnt, uint32_t *lcnt) {
-    const DevBox &B = boxes[blockIdx.y];
-    const int c = blockIdx.x * 256 + threadIdx.x;
-    if (c >= B.ncell) return;
-    const int n = B.cell_start[c + 1] - B.cell_start[c];
-    hcnt[B.cellbase + c] = n > kUnit ? (uint32_t)((n + kUnit - 1) / kUnit) : 0u;
-    lcnt[B.cellbase + c] = (n > 0 && n <= kUnit) ? 1u : 0u;
+// Sources in the 5x5x5 block of cell (cx, cy, cz): 25 row ranges of 5 cells.
+__device__ int block_sources(const int32_t *cs, int K, int cx, int cy, int cz) {
+    int s = 0;
+    for (int r = 0; r < kRows; ++r) {
+        const int rb = (wrapk(cx + r / 5 - 2, K) * K + wrapk(cy + r % 5 - 2, K)) * K;
+        const int lo = cz - 2, hi = cz + 2;
+        if (lo < 0)
+            s += (cs[rb + K] - cs[rb + lo + K]) + (cs[rb + hi + 1] - cs[rb]);
+        else if (hi >= K)
+            s += (cs[rb + K] - cs[rb + lo]) + (cs[rb + hi - K + 1] - cs[rb]);
+        else
+            s += cs[rb + hi + 1] - cs[rb + lo];
+    }
+    return s;
 }
 
+// Cost bucket of a dense cell: quarter octaves of its block's source count.
+constexpr int kBuckets = 128;
+__device__ __forceinline__ int cost_bucket(int sources) {
+    const float l = __log2f((float)max(sources, 1));
+    return min(kBuckets - 1, (int)(4.0f * l));
+}
+
+// Per cell: light cells (1..32 particles) count one light item; dense cells
+// add their ceil(n / 64) chunks to their cost bucket.
 __global__ void __launch_bounds__(256)
-k_plan_emit(const DevBox *boxes, const uint32_t *__restrict__ hscan,
-            const uint32_t *__restrict__ lscan, int64_t TG, Item *items) {
+k_plan_count(const DevBox *boxes, uint32_t *lcnt, uint32_t *bucket_cnt) {
     const DevBox &B = boxes[blockIdx.y];
     const int c = blockIdx.x * 256 + threadIdx.x;
     if (c >= B.ncell) return;
     const int n = B.cell_start[c + 1] - B.cell_start[c];
-    if (n > kUnit) {
-        Item *o = items + hscan[B.cellbase + c];
-        const int nch = (n + kUnit - 1) / kUnit;
-        for (int k = 0; k < nch; ++k) o[k] = Item{(int)blockIdx.y, c, 1, k};
-    } else if (n > 0) {
-        items[hscan[TG] + lscan[B.cellbase + c]] = Item{(int)blockIdx.y, c, 1, 0};
+    lcnt[B.cellbase + c] = (n > 0 && n < kDenseMin) ? 1u : 0u;
+    if (n >= kDenseMin) {
+        const int K = B.K;
+        const int b = cost_bucket(block_sources(B.cell_start, K, c / (K * K), (c / K) % K, c % K));
+        atomicAdd(&bucket_cnt[b], (uint32_t)((n + kUnit - 1) / kUnit));
     }
 }
 
-// ------------------------------------------------------------------ tiles
+// Bucket offsets, heaviest bucket first; totals[0] = dense items,
+// totals[1] = light items (from the scanned light counts).
+__global__ void __launch_bounds__(kBuckets)
+k_plan_buckets(uint32_t *bucket_cnt, uint32_t *bucket_off, const uint32_t *__restrict__ lscan,
+               int64_t C, uint32_t *totals) {
+    __shared__ uint32_t c[kBuckets];
+    const int t = threadIdx.x;
+    c[t] = bucket_cnt[t];
+    __syncthreads();
+    uint32_t off = 0;
+    for (int b = kBuckets - 1; b > t; --b) off += c[b];
+    bucket_off[t] = off;
+    bucket_cnt[t] = 0;   // reused as the fill cursor by k_plan_emit
+    if (t == 0) {
+        uint32_t tot = 0;
+        for (int b = 0; b < kBuckets; ++b) tot += c[b];
+        totals[0] = tot;
+        totals[1] = lscan[C];
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_plan_emit(const DevBox *boxes, const uint32_t *__restrict__ lscan,
+            const uint32_t *__restrict__ bucket_off, uint32_t *bucket_cur, Item *dense,
+            Item *light) {
+    const DevBox &B = boxes[blockIdx.y];
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    if (c >= B.ncell) return;
+    const int n = B.cell_start[c + 1] - B.cell_start[c];
+    if (n >= kDenseMin) {
+        const int K = B.K;
+        const int b = cost_bucket(block_sources(B.cell_start, K, c / (K * K), (c / K) % K, c % K));
+        const int nch = (n + kUnit - 1) / kUnit;
+        Item *o = dense + bucket_off[b] + atomicAdd(&bucket_cur[b], (uint32_t)nch);
+        for (int k = 0; k < nch; ++k) o[k] = Item{(int)blockIdx.y, c, 1, k};
+    } else if (n > 0) {
+        light[lscan[B.cellbase + c]] = Item{(int)blockIdx.y, c, 1, 0};
+    }
+}
+
+// ------------------------------------------------------------------ pair arithmetic
 
 struct Acc {
     float x = 0.f, y = 0.f, z = 0.f;
@@ -97,9 +153,10 @@ struct Coef {
 // One pair of the acceleration sum; SPLINE selects the single-min form of
 // Eq. 2, otherwise the pair is known to lie outside eps (Newton branch).
 template <bool SPLINE>
-__device__ __forceinline__ void pair_accel(const float4 s, float xi, float yi, float zi,
-                                           const Coef &k, float &px, float &py, float &pz) {
-    const float rx = s.x - xi, ry = s.y - yi, rz = s.z - zi;
+__device__ __forceinline__ void pair_accel(float sx, float sy, float sz, float xi, float yi,
+                                           float zi, const Coef &k, float &px, float &py,
+                                           float &pz) {
+    const float rx = sx - xi, ry = sy - yi, rz = sz - zi;
     float r2 = __builtin_fmaf(rx, rx, kTinyT);
     r2 = __builtin_fmaf(ry, ry, r2);
     r2 = __builtin_fmaf(rz, rz, r2);
@@ -117,13 +174,16 @@ __device__ __forceinline__ void pair_accel(const float4 s, float xi, float yi, f
     pz = __builtin_fmaf(f, rz, pz);
 }
 
-// One pair of the VJP: xbar_i += g (v_j - v_i) + h (r . (v_j - v_i)) r.
+// One pair of the VJP: xbar_i += g (v_j - v_i) + h (r . (v_j - v_i)) r, with
+// g = F/r and h = g'(rho)/rho.  Inside eps: g = cA + cB rho + cC rho^2 and
+// h = cB / rho + 2 cC = cB q + 2 cC; outside: g = q^3, h = -3 q^5.
 template <bool SPLINE>
-__device__ __forceinline__ void pair_vjp(const float4 s, const float2 v, float xi, float yi,
-                                         float zi, float vxi, float vyi, float vzi,
-                                         const Coef &k, float &px, float &py, float &pz) {
-    const float rx = s.x - xi, ry = s.y - yi, rz = s.z - zi;
-    const float ux = s.w - vxi, uy = v.x - vyi, uz = v.y - vzi;
+__device__ __forceinline__ void pair_vjp(float sx, float sy, float sz, float vx, float vy,
+                                         float vz, float xi, float yi, float zi, float vxi,
+                                         float vyi, float vzi, const Coef &k, float &px,
+                                         float &py, float &pz) {
+    const float rx = sx - xi, ry = sy - yi, rz = sz - zi;
+    const float ux = vx - vxi, uy = vy - vyi, uz = vz - vzi;
     float r2 = __builtin_fmaf(rx, rx, kTinyT);
     r2 = __builtin_fmaf(ry, ry, r2);
     r2 = __builtin_fmaf(rz, rz, r2);
@@ -147,8 +207,141 @@ __device__ __forceinline__ void pair_vjp(const float4 s, const float2 v, float x
     pz = __builtin_fmaf(t, rz, __builtin_fmaf(g, uz, pz));
 }
 
-// Sum over staged sources [lo, hi) (LDS indices) for one lane's sink, the
-// lane taking indices lo + b, lo + b + P, ...
+// Final value of a lane's sum (compensation folded in).
+template <bool COMP>
+__device__ __forceinline__ float3 value(const Acc &a) {
+    if constexpr (COMP) return make_float3(a.x - a.cx, a.y - a.cy, a.z - a.cz);
+    return make_float3(a.x, a.y, a.z);
+}
+
+__device__ __forceinline__ void store(const DevBox &B, int slot, float3 f) {
+    const int i = B.order[slot];
+    if (i >= 0 && i < B.n) {   // always true for a consistent binning
+        float *o = B.out + 3 * (int64_t)i;
+        o[0] = f.x * B.scale;
+        o[1] = f.y * B.scale;
+        o[2] = f.z * B.scale;
+    }
+}
+
+// ------------------------------------------------------------------ dense path
+
+typedef const __attribute__((address_space(4))) float cfloat;
+
+// Sources [j0, j1) of one cell through scalar loads.
+template <int MODE, bool SPLINE, bool COMP>
+__device__ __forceinline__ void run_scalar(cfloat *__restrict__ src, cfloat *__restrict__ cot,
+                                           int j0, int j1, float xs, float ys, float zs,
+                                           float4 vi, const Coef &k, Acc &acc) {
+    int j = j0;
+    while (j < j1) {
+        const int blk = min(j1 - j, kFlush);
+        float px = 0.f, py = 0.f, pz = 0.f;
+        if constexpr (!COMP) {
+            px = acc.x;
+            py = acc.y;
+            pz = acc.z;
+        }
+#pragma unroll(MODE == 0 ? 4 : 2)
+        for (int t = 0; t < blk; ++t, ++j) {
+            if constexpr (MODE == 0) {
+                pair_accel<SPLINE>(src[4 * j], src[4 * j + 1], src[4 * j + 2], xs, ys, zs, k, px,
+                                   py, pz);
+            } else {
+                pair_vjp<SPLINE>(src[4 * j], src[4 * j + 1], src[4 * j + 2], cot[4 * j],
+                                 cot[4 * j + 1], cot[4 * j + 2], xs, ys, zs, vi.x, vi.y, vi.z, k,
+                                 px, py, pz);
+            }
+        }
+        if constexpr (COMP) {
+            fold<true>(acc, px, py, pz);
+        } else {
+            acc.x = px;
+            acc.y = py;
+            acc.z = pz;
+        }
+    }
+}
+
+template <int MODE, bool COMP>
+__global__ void __launch_bounds__(kUnit)
+k_dense(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
+        const uint32_t *__restrict__ totals, uint32_t *counter,
+        const float4 *__restrict__ cot_sorted) {
+    __shared__ int s_item;
+    const int lane = threadIdx.x;
+    const int nitems = (int)totals[0];
+    for (;;) {
+        if (lane == 0) s_item = (int)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int itx = uni(s_item);
+        __syncthreads();
+        if (itx >= nitems) break;
+        const Item I = items[itx];
+        const DevBox &B = boxes[I.box];
+        const int K = B.K;
+        const int cx = I.cell0 / (K * K), cy = (I.cell0 / K) % K, z = I.cell0 % K;
+        const int32_t *__restrict__ cs = B.cell_start;
+        const int s0 = uni(cs[I.cell0] + kUnit * I.chunk);
+        const int g = uni(min(cs[I.cell0 + 1] - s0, kUnit));
+        const bool active = lane < g;
+        const int slot = s0 + (active ? lane : 0);
+        const float4 oi = B.off[slot];
+        float4 vi = make_float4(0.f, 0.f, 0.f, 0.f);
+        if constexpr (MODE == 1) vi = cot_sorted[B.base + slot];
+        const Coef k{B.cA, B.cB, B.cC, 2.0f * B.cC, B.eps * B.eps};
+        const bool fast = B.outer_newton != 0;
+        cfloat *src = (cfloat *)B.off;
+        cfloat *cot = (cfloat *)(cot_sorted + B.base);
+        Acc acc;
+        if (active) {
+            for (int r = 0; r < kRows; ++r) {
+                const int dx = r / 5 - 2, dy = r % 5 - 2;
+                const int rb = (wrapk(cx + dx, K) * K + wrapk(cy + dy, K)) * K;
+                const bool in_row = dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1;
+                const float xs = oi.x - (float)dx, ys = oi.y - (float)dy;
+                for (int dz = -2; dz <= 2; ++dz) {
+                    const int c = rb + wrapk(z + dz, K);
+                    const int j0 = uni(cs[c]), j1 = uni(cs[c + 1]);
+                    if (j0 >= j1) continue;
+                    const float zs = oi.z - (float)dz;
+                    if (!fast || (in_row && dz >= -1 && dz <= 1))
+                        run_scalar<MODE, true, COMP>(src, cot, j0, j1, xs, ys, zs, vi, k, acc);
+                    else
+                        run_scalar<MODE, false, COMP>(src, cot, j0, j1, xs, ys, zs, vi, k, acc);
+                }
+            }
+            store(B, slot, value<COMP>(acc));
+        }
+    }
+}
+
+// ------------------------------------------------------------------ light path
+
+// Pieces of the staged union: per row r = (dx+2)*5 + (dy+2) up to four
+// contiguous global ranges.  Slots 0-1: the |dz| <= 1 part of an inner row
+// (|dx|, |dy| <= 1); slots 2-3: the rest of the row (dz = -2 and +2 for an
+// inner row, dz = -2..2 split at the periodic wrap for an outer row).
+constexpr int kSlots = 4;
+constexpr int kPiece = kRows * kSlots;
+
+template <int MODE, int CAP>
+struct LightSmem {
+    float4 sx[CAP];                  // (o_x + dx, o_y + dy, o_z + dz, v_x)
+    float2 sv[MODE == 1 ? CAP : 1];  // (v_y, v_z) for the VJP
+    int pu[kPiece];                  // staged start of each piece
+    int pn[kPiece];                  // particles in the piece
+    int pg[kPiece];                  // global start of the piece
+    float pb[kPiece];                // z shift minus the source's cell index
+    int cnt[2][kRows];               // per row: inner-part and outer-part counts
+    float red[3][kUnit];
+    int item;
+    int inner;                       // staged particles of the 27 inner cells
+    int total;
+};
+
+// Sum over staged sources [lo, hi) for one lane's sink, the lane taking
+// indices lo + b, lo + b + P, ...
 template <int MODE, bool SPLINE, bool COMP>
 __device__ __forceinline__ void segment(const float4 *__restrict__ sx, const float2 *__restrict__ sv,
                                         int lo, int hi, int b, int P, float xi, float yi,
@@ -167,10 +360,14 @@ __device__ __forceinline__ void segment(const float4 *__restrict__ sx, const flo
         }
 #pragma unroll 4
         for (int t = 0; t < blk; ++t) {
-            if constexpr (MODE == 0)
-                pair_accel<SPLINE>(sx[j], xi, yi, zi, k, px, py, pz);
-            else
-                pair_vjp<SPLINE>(sx[j], sv[j], xi, yi, zi, vi.x, vi.y, vi.z, k, px, py, pz);
+            const float4 s = sx[j];
+            if constexpr (MODE == 0) {
+                pair_accel<SPLINE>(s.x, s.y, s.z, xi, yi, zi, k, px, py, pz);
+            } else {
+                const float2 v = sv[j];
+                pair_vjp<SPLINE>(s.x, s.y, s.z, s.w, v.x, v.y, xi, yi, zi, vi.x, vi.y, vi.z, k,
+                                 px, py, pz);
+            }
             j += P;
         }
         it += blk;
@@ -184,46 +381,26 @@ __device__ __forceinline__ void segment(const float4 *__restrict__ sx, const flo
     }
     if (b < n - nfull * P) {
         float px = 0.f, py = 0.f, pz = 0.f;
-        if constexpr (MODE == 0)
-            pair_accel<SPLINE>(sx[j], xi, yi, zi, k, px, py, pz);
-        else
-            pair_vjp<SPLINE>(sx[j], sv[j], xi, yi, zi, vi.x, vi.y, vi.z, k, px, py, pz);
+        const float4 s = sx[j];
+        if constexpr (MODE == 0) {
+            pair_accel<SPLINE>(s.x, s.y, s.z, xi, yi, zi, k, px, py, pz);
+        } else {
+            const float2 v = sv[j];
+            pair_vjp<SPLINE>(s.x, s.y, s.z, s.w, v.x, v.y, xi, yi, zi, vi.x, vi.y, vi.z, k, px,
+                             py, pz);
+        }
         fold<COMP>(acc, px, py, pz);
     }
 }
 
-__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
-
-// Pieces of the staged union: per row r = (dx+2)*5 + (dy+2) up to four
-// contiguous global ranges.  Slots 0-1: the |dz| <= 1 part of an inner row
-// (|dx|, |dy| <= 1); slots 2-3: the rest of the row (dz = -2 and +2 for an
-// inner row, dz = -2..2 split at the periodic wrap for an outer row).
-constexpr int kSlots = 4;
-constexpr int kPiece = kRows * kSlots;
-
-template <int MODE, int CAP>
-struct TileSmem {
-    float4 sx[CAP];                  // (o_x + dx, o_y + dy, o_z + dz, v_x)
-    float2 sv[MODE == 1 ? CAP : 1];  // (v_y, v_z) for the VJP
-    int pu[kPiece];                  // staged start of each piece
-    int pn[kPiece];                  // particles in the piece
-    int pg[kPiece];                  // global start of the piece
-    float pb[kPiece];                // z shift minus the source's cell index
-    int cnt[2][kRows];               // per row: inner-part and outer-part counts
-    float red[3][kUnit];
-    int item;
-    int inner;                       // staged particles of the 27 inner cells
-    int total;
-};
-
 template <int MODE, bool COMP, int CAP>
 __global__ void __launch_bounds__(kUnit)
-k_tile(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
-       const uint32_t *__restrict__ hscan, const uint32_t *__restrict__ lscan, int64_t TG,
-       uint32_t *counter, const float4 *__restrict__ cot_sorted) {
-    __shared__ TileSmem<MODE, CAP> sm;
+k_light(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
+        const uint32_t *__restrict__ totals, uint32_t *counter,
+        const float4 *__restrict__ cot_sorted) {
+    __shared__ LightSmem<MODE, CAP> sm;
     const int lane = threadIdx.x;
-    const int nitems = (int)(hscan[TG] + lscan[TG]);
+    const int nitems = (int)totals[1];
 
     for (;;) {
         if (lane == 0) sm.item = (int)atomicAdd(counter, 1u);
@@ -236,6 +413,8 @@ k_tile(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
         const int cx = I.cell0 / (K * K), cy = (I.cell0 / K) % K, z = I.cell0 % K;
         const int32_t *__restrict__ cs = B.cell_start;
         const float4 *__restrict__ off = B.off;
+        const int s0 = uni(cs[I.cell0]);
+        const int g = uni(cs[I.cell0 + 1]) - s0;
 
         // ---- pieces, one lane per row
         if (lane < kRows) {
@@ -243,32 +422,32 @@ k_tile(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
             const int dx = r / 5 - 2, dy = r % 5 - 2;
             const bool in_row = dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1;
             const int rb = (wrapk(cx + dx, K) * K + wrapk(cy + dy, K)) * K;
-            int g[kSlots], n[kSlots];
-            float bias[kSlots];
+            int pg[kSlots], pn[kSlots];
+            float pb[kSlots];
             // a run of z cells [za, zb] relative to the sink (za <= zb), split at the wrap
-            auto run = [&](int s0, int za, int zb) {
+            auto run = [&](int q, int za, int zb) {
                 const int lo = z + za, hi = z + zb;
-                if (lo < 0) {                       // [lo+K, K-1] then [0, hi]
-                    g[s0] = cs[rb + lo + K];
-                    n[s0] = cs[rb + K] - g[s0];
-                    bias[s0] = -(float)(z + K);
-                    g[s0 + 1] = cs[rb];
-                    n[s0 + 1] = cs[rb + hi + 1] - g[s0 + 1];
-                    bias[s0 + 1] = -(float)z;
-                } else if (hi >= K) {               // [lo, K-1] then [0, hi-K]
-                    g[s0] = cs[rb + lo];
-                    n[s0] = cs[rb + K] - g[s0];
-                    bias[s0] = -(float)z;
-                    g[s0 + 1] = cs[rb];
-                    n[s0 + 1] = cs[rb + hi - K + 1] - g[s0 + 1];
-                    bias[s0 + 1] = (float)(K - z);
+                if (lo < 0) {   // [lo+K, K-1] then [0, hi]
+                    pg[q] = cs[rb + lo + K];
+                    pn[q] = cs[rb + K] - pg[q];
+                    pb[q] = -(float)(z + K);
+                    pg[q + 1] = cs[rb];
+                    pn[q + 1] = cs[rb + hi + 1] - pg[q + 1];
+                    pb[q + 1] = -(float)z;
+                } else if (hi >= K) {   // [lo, K-1] then [0, hi-K]
+                    pg[q] = cs[rb + lo];
+                    pn[q] = cs[rb + K] - pg[q];
+                    pb[q] = -(float)z;
+                    pg[q + 1] = cs[rb];
+                    pn[q + 1] = cs[rb + hi - K + 1] - pg[q + 1];
+                    pb[q + 1] = (float)(K - z);
                 } else {
-                    g[s0] = cs[rb + lo];
-                    n[s0] = cs[rb + hi + 1] - g[s0];
-                    bias[s0] = -(float)z;
-                    g[s0 + 1] = 0;
-                    n[s0 + 1] = 0;
-                    bias[s0 + 1] = 0.f;
+                    pg[q] = cs[rb + lo];
+                    pn[q] = cs[rb + hi + 1] - pg[q];
+                    pb[q] = -(float)z;
+                    pg[q + 1] = 0;
+                    pn[q + 1] = 0;
+                    pb[q + 1] = 0.f;
                 }
             };
             if (in_row) {
@@ -276,25 +455,25 @@ k_tile(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
                 // the two single cells at dz = -2 and dz = +2
                 const int zm = z - 2, zp = z + 2;
                 const int cm = rb + wrapk(zm, K), cp = rb + wrapk(zp, K);
-                g[2] = cs[cm];
-                n[2] = cs[cm + 1] - g[2];
-                bias[2] = -(float)z + (zm < 0 ? -(float)K : 0.f);
-                g[3] = cs[cp];
-                n[3] = cs[cp + 1] - g[3];
-                bias[3] = -(float)z + (zp >= K ? (float)K : 0.f);
+                pg[2] = cs[cm];
+                pn[2] = cs[cm + 1] - pg[2];
+                pb[2] = -(float)z + (zm < 0 ? -(float)K : 0.f);
+                pg[3] = cs[cp];
+                pn[3] = cs[cp + 1] - pg[3];
+                pb[3] = -(float)z + (zp >= K ? (float)K : 0.f);
             } else {
-                g[0] = g[1] = 0;
-                n[0] = n[1] = 0;
-                bias[0] = bias[1] = 0.f;
+                pg[0] = pg[1] = 0;
+                pn[0] = pn[1] = 0;
+                pb[0] = pb[1] = 0.f;
                 run(2, -2, 2);
             }
             for (int q = 0; q < kSlots; ++q) {
-                sm.pn[r * kSlots + q] = n[q];
-                sm.pg[r * kSlots + q] = g[q];
-                sm.pb[r * kSlots + q] = bias[q];
+                sm.pn[r * kSlots + q] = pn[q];
+                sm.pg[r * kSlots + q] = pg[q];
+                sm.pb[r * kSlots + q] = pb[q];
             }
-            sm.cnt[0][r] = n[0] + n[1];
-            sm.cnt[1][r] = n[2] + n[3];
+            sm.cnt[0][r] = pn[0] + pn[1];
+            sm.cnt[1][r] = pn[2] + pn[3];
         }
         __syncthreads();
         if (lane < kRows) {
@@ -352,14 +531,6 @@ k_tile(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
 
         const Coef k{B.cA, B.cB, B.cC, 2.0f * B.cC, B.eps * B.eps};
         const bool fast = B.outer_newton != 0;
-        int s0 = cs[I.cell0], s1 = cs[I.cell0 + 1];
-        if (s1 - s0 > kUnit) {
-            s0 += kUnit * I.chunk;
-            s1 = min(s1, s0 + kUnit);
-        }
-        s0 = uni(s0);
-        s1 = uni(s1);
-        const int g = s1 - s0;
         const int P = kUnit / g;
         const bool active = lane < g * P;
         const int a = active ? lane % g : 0;
@@ -376,108 +547,87 @@ k_tile(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
             }
             if (active) {
                 const int split = fast ? inner : total;
-                const int lo = 0, mid = min(max(split, u0), u1) - u0, hi = u1 - u0;
-                if (mid > lo)
-                    segment<MODE, true, COMP>(sm.sx, sm.sv, lo, mid, b, P, oi.x, oi.y, oi.z, vi,
-                                              k, acc);
+                const int mid = min(max(split, u0), u1) - u0, hi = u1 - u0;
+                if (mid > 0)
+                    segment<MODE, true, COMP>(sm.sx, sm.sv, 0, mid, b, P, oi.x, oi.y, oi.z, vi, k,
+                                              acc);
                 if (hi > mid)
                     segment<MODE, false, COMP>(sm.sx, sm.sv, mid, hi, b, P, oi.x, oi.y, oi.z, vi,
                                                k, acc);
             }
         }
         // ---- fixed-order sum over slices
-        float fx, fy, fz;
-        if constexpr (COMP) {
-            fx = acc.x - acc.cx;
-            fy = acc.y - acc.cy;
-            fz = acc.z - acc.cz;
-        } else {
-            fx = acc.x;
-            fy = acc.y;
-            fz = acc.z;
-        }
-        if (P > 1) {
-            sm.red[0][lane] = fx;
-            sm.red[1][lane] = fy;
-            sm.red[2][lane] = fz;
-            __syncthreads();
-            if (lane < g) {
-                Acc t;
-                for (int sl = 0; sl < P; ++sl)
-                    fold<COMP>(t, sm.red[0][lane + sl * g], sm.red[1][lane + sl * g],
-                               sm.red[2][lane + sl * g]);
-                if constexpr (COMP) {
-                    fx = t.x - t.cx;
-                    fy = t.y - t.cy;
-                    fz = t.z - t.cz;
-                } else {
-                    fx = t.x;
-                    fy = t.y;
-                    fz = t.z;
-                }
-            }
-        }
+        float3 f = value<COMP>(acc);
+        sm.red[0][lane] = f.x;
+        sm.red[1][lane] = f.y;
+        sm.red[2][lane] = f.z;
+        __syncthreads();
         if (lane < g) {
-            const int i = B.order[s0 + lane];
-            if (i >= 0 && i < B.n) {
-                float *o = B.out + 3 * (int64_t)i;
-                o[0] = fx * B.scale;
-                o[1] = fy * B.scale;
-                o[2] = fz * B.scale;
-            }
+            Acc t;
+            for (int sl = 0; sl < P; ++sl)
+                fold<COMP>(t, sm.red[0][lane + sl * g], sm.red[1][lane + sl * g],
+                           sm.red[2][lane + sl * g]);
+            store(B, s0 + lane, value<COMP>(t));
         }
         __syncthreads();
     }
 }
 
-template <int MODE, bool COMP, int CAP>
-int tile_grid() {
-    static int grid = 0;
-    if (grid == 0) {
-        int dev = 0, ncu = 0, per = 0;
-        (void)hipGetDevice(&dev);
-        (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_tile<MODE, COMP, CAP>, kUnit, 0);
-        grid = std::max(1, ncu) * std::max(1, per);
-    }
-    return grid;
+// ------------------------------------------------------------------ launches
+
+template <typename Kern>
+int persistent_grid(Kern kern) {
+    int dev = 0, ncu = 0, per = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, kUnit, 0);
+    return std::max(1, ncu) * std::max(1, per);
 }
 
 template <int MODE, bool COMP>
-hipError_t launch_tile(const DevBox *d_boxes, const TilePlan &tp, const float4 *cot, hipStream_t s) {
+hipError_t launch_force(const DevBox *d_boxes, const TilePlan &tp, const float4 *cot,
+                        hipStream_t s) {
     constexpr int CAP = MODE == 0 ? 1024 : 768;
-    const int grid = tile_grid<MODE, COMP, CAP>();
-    hipLaunchKernelGGL((k_tile<MODE, COMP, CAP>), dim3(grid), dim3(kUnit), 0, s, d_boxes,
-                       (const Item *)tp.items, (const uint32_t *)tp.hcnt,
-                       (const uint32_t *)tp.lcnt, tp.TG, tp.counter, cot);
+    static const int gd = persistent_grid(k_dense<MODE, COMP>);
+    static const int gl = persistent_grid(k_light<MODE, COMP, CAP>);
+    hipLaunchKernelGGL((k_dense<MODE, COMP>), dim3(gd), dim3(kUnit), 0, s, d_boxes,
+                       (const Item *)tp.dense, (const uint32_t *)tp.totals, tp.counter, cot);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_light<MODE, COMP, CAP>), dim3(gl), dim3(kUnit), 0, s, d_boxes,
+                       (const Item *)tp.light, (const uint32_t *)tp.totals, tp.counter + 1, cot);
     return hipGetLastError();
 }
 
 }  // namespace
 
+int plan_buckets() { return kBuckets; }
+
 hipError_t plan_launch(const DevBox *d_boxes, int nbox, const TilePlan &tp, hipStream_t s) {
     hipError_t e;
     dim3 grid((unsigned)((tp.max_cells + 255) / 256), (unsigned)nbox);
-    if ((e = fill_u32(tp.hcnt + tp.TG, 1, 0u, s)) != hipSuccess) return e;
     if ((e = fill_u32(tp.lcnt + tp.TG, 1, 0u, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_plan_count, grid, dim3(256), 0, s, d_boxes, tp.hcnt, tp.lcnt);
+    if ((e = fill_u32(tp.bucket_cnt, kBuckets, 0u, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_plan_count, grid, dim3(256), 0, s, d_boxes, tp.lcnt, tp.bucket_cnt);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = scan_exclusive(tp.hcnt, tp.TG + 1, tp.scan_scratch, s)) != hipSuccess) return e;
     if ((e = scan_exclusive(tp.lcnt, tp.TG + 1, tp.scan_scratch, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_plan_emit, grid, dim3(256), 0, s, d_boxes, (const uint32_t *)tp.hcnt,
-                       (const uint32_t *)tp.lcnt, tp.TG, tp.items);
+    hipLaunchKernelGGL(k_plan_buckets, dim3(1), dim3(kBuckets), 0, s, tp.bucket_cnt,
+                       tp.bucket_off, (const uint32_t *)tp.lcnt, tp.TG, tp.totals);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_plan_emit, grid, dim3(256), 0, s, d_boxes, (const uint32_t *)tp.lcnt,
+                       (const uint32_t *)tp.bucket_off, tp.bucket_cnt, tp.dense, tp.light);
     return hipGetLastError();
 }
 
 hipError_t tile_launch(const DevBox *d_boxes, int mode, bool compensated, const TilePlan &tp,
                        const float4 *cot, hipStream_t s) {
-    hipError_t e = fill_u32(tp.counter, 1, 0u, s);
+    hipError_t e = fill_u32(tp.counter, 2, 0u, s);
     if (e != hipSuccess) return e;
     if (mode == 0)
-        return compensated ? launch_tile<0, true>(d_boxes, tp, cot, s)
-                           : launch_tile<0, false>(d_boxes, tp, cot, s);
-    return compensated ? launch_tile<1, true>(d_boxes, tp, cot, s)
-                       : launch_tile<1, false>(d_boxes, tp, cot, s);
+        return compensated ? launch_force<0, true>(d_boxes, tp, cot, s)
+                           : launch_force<0, false>(d_boxes, tp, cot, s);
+    return compensated ? launch_force<1, true>(d_boxes, tp, cot, s)
+                       : launch_force<1, false>(d_boxes, tp, cot, s);
 }
 
 }  // namespace nf
