@@ -39,7 +39,108 @@ def parse():
     ap.add_argument("--cpu-sinks", type=int, default=1 << 18,
                     help="sinks in the oracle's timed sample")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="only run a plain 1 GiB device copy (HBM counter calibration)")
     return ap.parse_args()
+
+
+def kernel_source_hash() -> str:
+    """Hash of the HIP sources, to tell whether stored counters are current."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1810_02916_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(workload: str, kernel: str):
+    """HBM bytes per launch from profiles/traffic_<workload>.txt, written from
+    rocprofv3 FETCH_SIZE / WRITE_SIZE runs and scaled by the copy-kernel
+    calibration; None when absent or taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            parts = line.split()
+            if len(parts) == 2 and not line.startswith("#"):
+                vals[parts[0]] = parts[1]
+    if vals.get("source_hash") != kernel_source_hash():
+        return None
+    v = vals.get(f"{kernel}_bytes")
+    return float(v) if v is not None else None
+
+
+def copy_calibration():
+    import torch
+    n = 1 << 28   # 2^28 float32 = 1 GiB read + 1 GiB written per copy
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "copies": 5}))
+
+
+def bench_batched(args):
+    """64 uneven boxes: per-box calls vs one batched call vs one graph replay
+    (binning + compensated accelerations each time)."""
+    import numpy as np
+    import torch
+
+    from paper_1810_02916_amd import nearfield as nfp
+    from paper_1810_02916_amd.synth import batched_specs, make_box, occupancy_stats
+
+    specs = batched_specs(64)
+    dev = torch.device("cuda:0")
+    boxes = [make_box(s) for s in specs]
+    I = sum(occupancy_stats(p, s.K, s.L)["interactions"] for p, s in zip(boxes, specs))
+    pos = [torch.from_numpy(p).to(dev) for p in boxes]
+    Ks, Ls, Es = [s.K for s in specs], [s.L for s in specs], [s.eps_s for s in specs]
+
+    def per_box():
+        return [nfp.accel(nfp.bin_particles(p, K, L, e), 1.0, compensated=True)
+                for p, K, L, e in zip(pos, Ks, Ls, Es)]
+
+    def batched():
+        return nfp.accel(nfp.bin_particles_batched(pos, Ks, Ls, Es), 1.0, compensated=True)
+
+    cf = nfp.CapturedForce(pos, Ks, Ls, Es, 1.0, compensated=True)
+
+    def timeit(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / args.steps
+
+    t_box, t_bat, t_graph = timeit(per_box), timeit(batched), timeit(cf.replay)
+    ref = batched()
+    got = cf.replay()
+    torch.cuda.synchronize()
+    same = all(torch.equal(a, b) for a, b in zip(ref, got))
+    n = sum(s.n for s in specs)
+    print(json.dumps({
+        "metric": "G pair-interactions/s and particles/s (FP32 vs compensated, err vs FP64)",
+        "value": round(I / (t_graph * 1e-3) / 1e9, 3), "unit": "G pair-interactions/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(t_graph, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batched64", "boxes": len(specs), "n_total": n,
+                   "interactions": I, "step": "bin + accel compensated, all boxes"},
+        "ms": {"per_box_calls": round(t_box, 4), "one_batched_call": round(t_bat, 4),
+               "graph_replay": round(t_graph, 4)},
+        "gdips": {"per_box_calls": round(I / t_box / 1e6, 2),
+                  "one_batched_call": round(I / t_bat / 1e6, 2),
+                  "graph_replay": round(I / t_graph / 1e6, 2)},
+        "graph_equals_eager": same,
+    }), flush=True)
 
 
 def main():
@@ -49,20 +150,29 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.copy_calib:
+        copy_calibration()
+        return
+    if args.workload == "batched64":
+        bench_batched(args)
+        return
+
     import numpy as np
     import torch
 
     from paper_1810_02916_amd import nearfield as nfp
-    from paper_1810_02916_amd.synth import WORKLOADS, gaussian_cotangent, make_box, occupancy_stats
+    from paper_1810_02916_amd.synth import (WORKLOADS, make_box_device,
+                                            occupancy_stats_device)
 
     sp = WORKLOADS[args.workload]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    pos_np = make_box(sp)
-    occ = occupancy_stats(pos_np, sp.K, sp.L)
+    pos = make_box_device(sp, dev)
+    occ = occupancy_stats_device(pos, sp.K, sp.L)
     I = occ["interactions"]
-    pos = torch.from_numpy(pos_np).to(dev)
-    cot = torch.from_numpy(gaussian_cotangent(sp.n, sp.seed * 10 + 2).astype(np.float32)).to(dev)
+    cot = torch.randn((sp.n, 3), generator=torch.Generator(device=dev).manual_seed(sp.seed * 10 + 2),
+                      device=dev, dtype=torch.float32)
+    print(f"[bench] {sp.name}: n={sp.n} K={sp.K} interactions={I}", file=sys.stderr, flush=True)
     stream = torch.cuda.current_stream(dev)
 
     def step(ev=None):
@@ -140,8 +250,12 @@ def main():
         "bin_hbm_gbs": round(40.0 * sp.n / (t_bin * 1e-3) / 1e9, 1),
         "roofline": {"kernel": dom, "bound": "alu", "achieved": round(achieved / 1e12, 3),
                      "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK_FP32, 4), "traffic": None,
-                     "flop_per_pair": fdom, "pairs_per_launch": I},
+                     "frac": round(achieved / PEAK_FP32, 4),
+                     "traffic": stored_traffic(sp.name, dom),
+                     "flop_per_pair": fdom, "pairs_per_launch": I,
+                     "timed": "HIP events around the library call on its stream: planner "
+                              "kernels + dense and light force kernels"},
+        "kernel_source_hash": kernel_source_hash(),
     }
 
     if not args.no_cpu:
@@ -150,6 +264,8 @@ def main():
         rng = np.random.default_rng(12345)
         m = min(args.cpu_sinks, sp.n)
         sinks = np.sort(rng.choice(sp.n, m, replace=False))
+        pos_np = pos.cpu().numpy()
+        print(f"[bench] oracle on {m} sinks", file=sys.stderr, flush=True)
         tc0 = time.perf_counter()
         ref, cnt = oracle.accel(pos_np, sp.K, sp.L, sp.eps_s, sinks=sinks, return_count=True)
         tc1 = time.perf_counter()

@@ -104,7 +104,10 @@ enum {
 typedef struct nf_box {
     int64_t n;
     int32_t K;
-    int32_t reserved;   /* set to 0 */
+    int32_t dense_min;  /* tile choice: cells with at least this many particles are
+                           summed one sink per lane (sources broadcast), smaller
+                           cells spread over (sink, source-slice) lanes; 0 picks
+                           the library default (33); otherwise 2..65 */
     double L;
     double eps_s;
     const double *pos;

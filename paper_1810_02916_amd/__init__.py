@@ -7,6 +7,7 @@ include/nf.h); this package only marshals arguments to it.
 from .nearfield import (  # noqa: F401
     SPLINE_PER_PLUMMER,
     Binned,
+    CapturedForce,
     NearFieldAccel,
     accel,
     accel_vjp,
@@ -14,4 +15,5 @@ from .nearfield import (  # noqa: F401
     bin_particles_batched,
     eps_spline_from_plummer,
     nearfield_accel,
+    rebin,
 )

@@ -38,7 +38,7 @@ class NfBox(ctypes.Structure):
     _fields_ = [
         ("n", ctypes.c_int64),
         ("K", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("dense_min", ctypes.c_int32),
         ("L", ctypes.c_double),
         ("eps_s", ctypes.c_double),
         ("pos", ctypes.c_void_p),

@@ -114,6 +114,8 @@ int validate(int nbox, const nf_box *boxes, Layout &L) {
         if (ncell + 1 > INT32_MAX) return fail(NF_EUNSUPPORTED, std::string(where) + "K^3 + 1 exceeds 2^31 - 1");
         if (B.n > INT32_MAX) return fail(NF_EUNSUPPORTED, std::string(where) + "n exceeds 2^31 - 1");
         if (!B.cell_start) return fail(NF_EINVAL, std::string(where) + "cell_start is NULL");
+        if (B.dense_min != 0 && (B.dense_min < 2 || B.dense_min > 65))
+            return fail(NF_EINVAL, std::string(where) + "dense_min must be 0 or in [2, 65]");
         if (B.n > 0 && (!B.off || !B.order))
             return fail(NF_EINVAL, std::string(where) + "off/order is NULL");
         const double kappa = (double)B.K / B.L;
@@ -202,6 +204,7 @@ void fill_geometry(const nf_box &B, const Layout &L, int b, DevBox &d) {
     d.cB = (float)(-15.0 / (eps * eps * eps * eps));
     d.cC = (float)(6.0 / (eps * eps * eps * eps * eps));
     d.outer_newton = eps <= 1.0 ? 1 : 0;
+    d.dense_min = B.dense_min ? B.dense_min : 33;
     d.pos = B.pos;
     d.off = reinterpret_cast<float4 *>(B.off);
     d.cell_start = B.cell_start;

@@ -35,6 +35,7 @@ struct DevBox {
     float scale;          // gm * kappa^2 (accel) or gm * kappa^3 (vjp)
     float cA, cB, cC;     // Eq. 2 in cell widths: F/r = cA + cB r + cC r^2 inside eps
                           // (10/eps^3, -15/eps^4, 6/eps^5, rounded from double)
+    int32_t dense_min;    // cells with at least this many particles take the dense path
     int32_t outer_newton; // 1 when eps <= 1: every pair from the outer shell of
                           // the 5x5x5 block is at r >= 1 >= eps (Newton branch)
     // caller buffers

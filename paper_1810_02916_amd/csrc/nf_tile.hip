@@ -4,14 +4,14 @@
 // 5x5x5 cell block of Sec. 2.1.
 //
 // Work items (one wave each):
-//   * dense  -- 64 sinks (or the remainder) of a cell holding more than 32
-//               particles.  One sink per lane; every lane needs the same
+//   * dense  -- 64 sinks (or the remainder) of a cell holding at least
+//               dense_min particles (33 by default).  One sink per lane; every lane needs the same
 //               source at the same time, so sources are read from the
 //               cell-sorted array with scalar loads and enter the arithmetic
 //               as SGPR operands, and the sink is shifted into each source
 //               cell's frame.  No LDS, so many waves fit on a CU and hide the
 //               load latency.  Items run heaviest neighbourhood first.
-//   * light  -- all sinks of a cell holding 1..32 particles.  The 125 source
+//   * light  -- all sinks of a cell holding fewer particles (at most 64).  The 125 source
 //               cells are staged in LDS in the sink cell's own frame,
 //               (o_x + dx, o_y + dy, o_z + dz), the 27 cells with |d| <= 1
 //               first, then the 98 outer cells, so the sum is two contiguous
@@ -30,7 +30,6 @@ namespace nf {
 namespace {
 
 constexpr int kUnit = 64;            // sinks per wave
-constexpr int kDenseMin = 33;        // cells with more particles go to the dense path
 constexpr int kRows = 25;            // (dx, dy) rows of the 5x5x5 block
 constexpr float kTinyT = 1.0e-30f;   // floor on r^2: a coincident pair gives 0
 constexpr int kFlush = 32;           // compensated mode: plain partials of <= 32 terms
@@ -63,7 +62,7 @@ __device__ __forceinline__ int cost_bucket(int sources) {
     return min(kBuckets - 1, (int)(4.0f * l));
 }
 
-// Per cell: light cells (1..32 particles) count one light item; dense cells
+// Per cell: light cells (1 .. dense_min-1 particles) count one light item; dense cells
 // add their ceil(n / 64) chunks to their cost bucket.
 __global__ void __launch_bounds__(256)
 k_plan_count(const DevBox *boxes, uint32_t *lcnt, uint32_t *bucket_cnt) {
@@ -71,8 +70,8 @@ k_plan_count(const DevBox *boxes, uint32_t *lcnt, uint32_t *bucket_cnt) {
     const int c = blockIdx.x * 256 + threadIdx.x;
     if (c >= B.ncell) return;
     const int n = B.cell_start[c + 1] - B.cell_start[c];
-    lcnt[B.cellbase + c] = (n > 0 && n < kDenseMin) ? 1u : 0u;
-    if (n >= kDenseMin) {
+    lcnt[B.cellbase + c] = (n > 0 && n < B.dense_min) ? 1u : 0u;
+    if (n >= B.dense_min) {
         const int K = B.K;
         const int b = cost_bucket(block_sources(B.cell_start, K, c / (K * K), (c / K) % K, c % K));
         atomicAdd(&bucket_cnt[b], (uint32_t)((n + kUnit - 1) / kUnit));
@@ -108,7 +107,7 @@ k_plan_emit(const DevBox *boxes, const uint32_t *__restrict__ lscan,
     const int c = blockIdx.x * 256 + threadIdx.x;
     if (c >= B.ncell) return;
     const int n = B.cell_start[c + 1] - B.cell_start[c];
-    if (n >= kDenseMin) {
+    if (n >= B.dense_min) {
         const int K = B.K;
         const int b = cost_bucket(block_sources(B.cell_start, K, c / (K * K), (c / K) % K, c % K));
         const int nch = (n + kUnit - 1) / kUnit;
@@ -284,6 +283,9 @@ k_dense(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
         const int32_t *__restrict__ cs = B.cell_start;
         const int s0 = uni(cs[I.cell0] + kUnit * I.chunk);
         const int g = uni(min(cs[I.cell0 + 1] - s0, kUnit));
+        // Lanes beyond the g sinks repeat sink 0 and are dropped at the store:
+        // the loop below stays convergent, so every lane holds its row's cell
+        // ranges when they are read back with readlane.
         const bool active = lane < g;
         const int slot = s0 + (active ? lane : 0);
         const float4 oi = B.off[slot];
@@ -293,16 +295,30 @@ k_dense(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
         const bool fast = B.outer_newton != 0;
         cfloat *src = (cfloat *)B.off;
         cfloat *cot = (cfloat *)(cot_sorted + B.base);
+        // cell ranges of the 125 source cells: lane r < 25 holds row r's five
+        // (start, end) pairs, read back with readlane (uniform, no memory wait)
+        int cb[5], ce[5];
+        {
+            const int r = lane < kRows ? lane : 0;
+            const int rb = (wrapk(cx + r / 5 - 2, K) * K + wrapk(cy + r % 5 - 2, K)) * K;
+#pragma unroll
+            for (int q = 0; q < 5; ++q) {
+                const int c = rb + wrapk(z + q - 2, K);
+                cb[q] = cs[c];
+                ce[q] = cs[c + 1];
+            }
+        }
         Acc acc;
-        if (active) {
+        {
             for (int r = 0; r < kRows; ++r) {
                 const int dx = r / 5 - 2, dy = r % 5 - 2;
-                const int rb = (wrapk(cx + dx, K) * K + wrapk(cy + dy, K)) * K;
                 const bool in_row = dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1;
                 const float xs = oi.x - (float)dx, ys = oi.y - (float)dy;
-                for (int dz = -2; dz <= 2; ++dz) {
-                    const int c = rb + wrapk(z + dz, K);
-                    const int j0 = uni(cs[c]), j1 = uni(cs[c + 1]);
+#pragma unroll
+                for (int q = 0; q < 5; ++q) {
+                    const int dz = q - 2;
+                    const int j0 = max(__builtin_amdgcn_readlane(cb[q], r), 0);
+                    const int j1 = min(__builtin_amdgcn_readlane(ce[q], r), B.n);
                     if (j0 >= j1) continue;
                     const float zs = oi.z - (float)dz;
                     if (!fast || (in_row && dz >= -1 && dz <= 1))
@@ -311,8 +327,8 @@ k_dense(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
                         run_scalar<MODE, false, COMP>(src, cot, j0, j1, xs, ys, zs, vi, k, acc);
                 }
             }
-            store(B, slot, value<COMP>(acc));
         }
+        if (active) store(B, slot, value<COMP>(acc));
     }
 }
 

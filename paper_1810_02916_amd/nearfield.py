@@ -25,10 +25,12 @@ __all__ = [
     "Binned",
     "bin_particles",
     "bin_particles_batched",
+    "rebin",
     "accel",
     "accel_vjp",
     "NearFieldAccel",
     "nearfield_accel",
+    "CapturedForce",
 ]
 
 # Sec. 4.3: spline radius with the same minimum pairwise dynamical time as a
@@ -54,13 +56,14 @@ class _BoxBuffers:
     cell_start: torch.Tensor   # [K^3+1] int32
     order: torch.Tensor        # [n] int32
     nbad: torch.Tensor         # [1] int32
+    dense_min: int = 0         # tile choice (0: library default)
 
     @property
     def n(self) -> int:
         return int(self.pos.shape[0])
 
     def cstruct(self) -> NfBox:
-        return NfBox(self.n, self.K, 0, self.L, self.eps_s, self.pos.data_ptr(),
+        return NfBox(self.n, self.K, self.dense_min, self.L, self.eps_s, self.pos.data_ptr(),
                      self.off.data_ptr(), self.cell_start.data_ptr(), self.order.data_ptr(),
                      self.nbad.data_ptr())
 
@@ -113,8 +116,10 @@ def _alloc_box(pos: torch.Tensor, K: int, L: float, eps_s: float) -> _BoxBuffers
 
 
 def bin_particles_batched(positions: Sequence[torch.Tensor], Ks: Sequence[int],
-                          Ls: Sequence[float], eps: Sequence[float]) -> Binned:
-    """Bin several boxes in one call (one radix sort over all of them)."""
+                          Ls: Sequence[float], eps: Sequence[float],
+                          dense_min: int = 0) -> Binned:
+    """Bin several boxes in one call (one radix sort over all of them).
+    ``dense_min`` is the force kernels' tile choice (0: library default)."""
     lib = _lib.load()
     if not (len(positions) == len(Ks) == len(Ls) == len(eps)) or len(positions) == 0:
         raise ValueError("positions, Ks, Ls and eps must be non-empty and of equal length")
@@ -123,6 +128,8 @@ def bin_particles_batched(positions: Sequence[torch.Tensor], Ks: Sequence[int],
     if any(p.device != dev for p in ps):
         raise ValueError("all boxes must live on one device")
     boxes = [_alloc_box(p, K, L, e) for p, K, L, e in zip(ps, Ks, Ls, eps)]
+    for bx in boxes:
+        bx.dense_min = int(dense_min)
     arr = (NfBox * len(boxes))()
     for i, b in enumerate(boxes):
         arr[i] = b.cstruct()
@@ -139,9 +146,20 @@ def bin_particles_batched(positions: Sequence[torch.Tensor], Ks: Sequence[int],
     return out
 
 
-def bin_particles(pos: torch.Tensor, K: int, L: float, eps_s: float) -> Binned:
+def rebin(b: Binned) -> Binned:
+    """Bin again into the same buffers (positions updated in place)."""
+    lib = _lib.load()
+    with torch.cuda.device(b.device):
+        rc = lib.nf_bin_particles(b.nbox, b.carray(), ctypes.c_void_p(b.workspace.data_ptr()),
+                                  b.workspace.numel(), _stream_handle(b.device))
+    _lib.check(rc)
+    return b
+
+
+def bin_particles(pos: torch.Tensor, K: int, L: float, eps_s: float,
+                  dense_min: int = 0) -> Binned:
     """Bin one box: cell offsets (FP64 -> FP32) and a stable sort by cell."""
-    return bin_particles_batched([pos], [K], [L], [eps_s])
+    return bin_particles_batched([pos], [K], [L], [eps_s], dense_min)
 
 
 def _flags(compensated: bool, simple: bool) -> int:
@@ -219,3 +237,32 @@ class NearFieldAccel(torch.autograd.Function):
 def nearfield_accel(pos: torch.Tensor, K: int, L: float, eps_s: float, gm: float = 1.0,
                     compensated: bool = False) -> torch.Tensor:
     return NearFieldAccel.apply(pos, K, L, eps_s, gm, compensated)
+
+
+class CapturedForce:
+    """Binning + accelerations of a fixed set of boxes captured once into a
+    HIP graph; ``replay()`` recomputes both from the current contents of the
+    position buffers ``self.positions`` (update them in place).
+
+    Every library call is a pure sequence of kernel launches (descriptors go
+    through kernel arguments, buffers are filled by kernels), so the whole
+    step is one graph launch."""
+
+    def __init__(self, positions: Sequence[torch.Tensor], Ks, Ls, eps, gm: float = 1.0,
+                 compensated: bool = False):
+        self.positions = [_prep_pos(p) for p in positions]
+        self.gm = float(gm)
+        self.compensated = bool(compensated)
+        self.binned = bin_particles_batched(self.positions, Ks, Ls, eps)
+        self.out = [torch.empty((bx.n, 3), dtype=torch.float32, device=self.binned.device)
+                    for bx in self.binned.boxes]
+        accel(self.binned, self.gm, compensated=self.compensated, out=self.out)   # warm up
+        torch.cuda.synchronize(self.binned.device)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            rebin(self.binned)
+            accel(self.binned, self.gm, compensated=self.compensated, out=self.out)
+
+    def replay(self) -> List[torch.Tensor]:
+        self.graph.replay()
+        return self.out

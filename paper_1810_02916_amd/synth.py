@@ -33,8 +33,11 @@ __all__ = [
     "BoxSpec",
     "WORKLOADS",
     "make_box",
+    "make_box_device",
+    "clustered_box_device",
     "batched_specs",
     "occupancy_stats",
+    "occupancy_stats_device",
 ]
 
 
@@ -148,6 +151,78 @@ def clustered_box(n: int, side: int, K: int, L: float, sigma_ln: float,
     return np.ascontiguousarray(pos[perm])
 
 
+def clustered_box_device(n: int, side: int, K: int, L: float, sigma_ln: float,
+                         psi_rms_cells: float, seed: int, device="cuda:0",
+                         spectral_index: float = -2.0):
+    """The clustered recipe of ``clustered_box`` drawn with torch on a device,
+    for boxes too large for host-side generation.  Returns an ``(n, 3)``
+    float64 tensor on ``device``.  The multinomial cell counts are sampled
+    exactly by locating n uniform draws in the cumulative cell weights; the
+    draws are independent, so the particles come out in random order.  Its
+    random stream differs from ``clustered_box`` (same recipe, other
+    generator)."""
+    import torch
+    dev = torch.device(device)
+    g = torch.Generator(device=dev)
+    g.manual_seed(int(seed))
+    side, K, n = int(side), int(K), int(n)
+    w = torch.randn((side, side, side), generator=g, device=dev, dtype=torch.float64)
+    wk = torch.fft.rfftn(w)
+    del w
+    f = torch.fft.fftfreq(side, d=1.0 / side, device=dev, dtype=torch.float64)
+    fz = torch.fft.rfftfreq(side, d=1.0 / side, device=dev, dtype=torch.float64)
+    kx, ky, kz = f[:, None, None], f[None, :, None], fz[None, None, :]
+    k2 = kx * kx + ky * ky + kz * kz
+    amp = torch.where(k2 > 0, k2.clamp_min(1e-300) ** (spectral_index / 4.0), torch.zeros_like(k2))
+    if side % 2 == 0:
+        nyq = side // 2
+        amp = amp * (kx.abs() != nyq) * (ky.abs() != nyq) * (kz.abs() != nyq)
+    dk = wk * amp
+    del wk, amp
+    inv_k2 = torch.where(k2 > 0, 1.0 / k2.clamp_min(1e-300), torch.zeros_like(k2))
+    spacing, cell = L / side, L / K
+    lat1 = (torch.arange(side, device=dev, dtype=torch.float64) + 0.5) * spacing
+    psi = [torch.fft.irfftn(1j * ka * inv_k2 * dk, s=(side, side, side)) for ka in (kx, ky, kz)]
+    rms = float(torch.sqrt(sum((p * p).mean() for p in psi)))
+    scale = psi_rms_cells * cell / rms if rms > 0 else 0.0
+    cidx = torch.zeros((side, side, side), dtype=torch.int64, device=dev)
+    for a, p in enumerate(psi):
+        shape = [1, 1, 1]
+        shape[a] = side
+        x = torch.remainder(lat1.reshape(shape) + scale * p, L)
+        ca = torch.clamp((x * (K / L)).to(torch.int64), max=K - 1)
+        cidx = cidx * K + ca
+    del psi
+    m = torch.bincount(cidx.reshape(-1), minlength=K ** 3).to(torch.float64)
+    del cidx
+    delta = torch.fft.irfftn(dk, s=(side, side, side))
+    del dk
+    c1 = torch.clamp((lat1 * (K / L)).to(torch.int64), max=K - 1)
+    lat_cell = ((c1[:, None, None] * K + c1[None, :, None]) * K + c1[None, None, :]).reshape(-1)
+    ssum = torch.bincount(lat_cell, weights=delta.reshape(-1), minlength=K ** 3)
+    cnt = torch.bincount(lat_cell, minlength=K ** 3)
+    del delta, lat_cell
+    G = torch.where(cnt > 0, ssum / cnt.clamp_min(1), torch.zeros_like(ssum))
+    G = (G - G.mean()) / (G.std() if float(G.std()) > 0 else 1.0)
+    logw = torch.where(m > 0, torch.log(m.clamp_min(1.0)) + sigma_ln * G,
+                       torch.full_like(m, -float("inf")))
+    wts = torch.exp(logw - logw[torch.isfinite(logw)].max())
+    cdf = torch.cumsum(wts, 0)
+    u = torch.rand(n, generator=g, device=dev, dtype=torch.float64) * cdf[-1]
+    cells = torch.clamp(torch.searchsorted(cdf, u, right=True), max=K ** 3 - 1)
+    del u, cdf
+    cz = cells % K
+    cy = (cells // K) % K
+    cx = cells // (K * K)
+    del cells
+    pos = torch.rand((n, 3), generator=g, device=dev, dtype=torch.float64)
+    pos[:, 0] += cx
+    pos[:, 1] += cy
+    pos[:, 2] += cz
+    pos *= cell
+    return pos
+
+
 def gaussian_cotangent(n: int, seed: int) -> np.ndarray:
     """Seeded N(0,1) cotangent / tangent vectors, ``(n, 3)`` float64."""
     (g,) = _streams(seed, 1)
@@ -182,10 +257,21 @@ class BoxSpec:
 
 
 def make_box(spec: BoxSpec) -> np.ndarray:
+    if spec.kind == "clustered_device":
+        return make_box_device(spec).cpu().numpy()
     if spec.kind == "uniform":
         return uniform_box(spec.n, spec.L, spec.seed)
     return clustered_box(spec.n, spec.side, spec.K, spec.L, spec.sigma_ln,
                          spec.psi_rms_cells, spec.seed)
+
+
+def make_box_device(spec: BoxSpec, device="cuda:0"):
+    """Positions as a float64 tensor on ``device``."""
+    import torch
+    if spec.kind == "clustered_device":
+        return clustered_box_device(spec.n, spec.side, spec.K, spec.L, spec.sigma_ln,
+                                    spec.psi_rms_cells, spec.seed, device)
+    return torch.from_numpy(make_box(spec)).to(device)
 
 
 WORKLOADS = {
@@ -195,8 +281,9 @@ WORKLOADS = {
     "clustered2m": BoxSpec("clustered2m", 128 ** 3, 64, 1.0, 0.041 / 128, "clustered",
                            side=128, sigma_ln=1.5, psi_rms_cells=0.5, seed=1812),
     # 512^3 clustered particles in a 125 Mpc/h box, 256^3 cells, sigma_ln = 2.0
+    # (drawn on the device: host-side generation of 512^3 takes minutes)
     "clustered134m": BoxSpec("clustered134m", 512 ** 3, 256, 125.0, 0.041 * 125.0 / 512,
-                             "clustered", side=512, sigma_ln=2.0, psi_rms_cells=0.5,
+                             "clustered_device", side=512, sigma_ln=2.0, psi_rms_cells=0.5,
                              seed=1814),
     # 64^3 clustered particles, 32^3 cells (differentiation workload)
     "clustered262k": BoxSpec("clustered262k", 64 ** 3, 32, 1.0, 0.041 / 64, "clustered",
@@ -218,6 +305,31 @@ def batched_specs(nbox: int = 64, seed: int = 1813, lo: int = 32 ** 3,
                            side=side, sigma_ln=1.5, psi_rms_cells=0.5,
                            seed=seed * 1000 + b))
     return out
+
+
+def occupancy_stats_device(pos, K: int, L: float) -> dict:
+    """``occupancy_stats`` for a float64 torch tensor, computed on its device."""
+    import torch
+    c = torch.remainder(torch.floor(pos * (K / L)).to(torch.int64), K)
+    cnt = torch.bincount((c[:, 0] * K + c[:, 1]) * K + c[:, 2], minlength=K ** 3).reshape(K, K, K)
+    del c
+    s = cnt.clone()
+    for ax in range(3):
+        acc = torch.zeros_like(s)
+        for d in range(-2, 3):
+            acc += torch.roll(s, d, dims=ax)
+        s = acc
+    nz = cnt[cnt > 0].to(torch.float64)
+    I = int((cnt * s).sum())
+    return {
+        "n": int(pos.shape[0]),
+        "cells": int(K ** 3),
+        "max_cell": int(cnt.max()),
+        "empty_frac": float((cnt == 0).to(torch.float64).mean()),
+        "std_ln_count": float(torch.log(nz).std()) if nz.numel() else 0.0,
+        "interactions": I,
+        "interactions_per_particle": I / max(1, int(pos.shape[0])),
+    }
 
 
 def occupancy_stats(pos: np.ndarray, K: int, L: float) -> dict:

@@ -54,7 +54,7 @@ def test_struct_layout_matches_header(lib, tmp_path):
     prog.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "nf.h"\n'
         "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\","
-        "sizeof(nf_box), offsetof(nf_box,n), offsetof(nf_box,K), offsetof(nf_box,reserved),"
+        "sizeof(nf_box), offsetof(nf_box,n), offsetof(nf_box,K), offsetof(nf_box,dense_min),"
         "offsetof(nf_box,L), offsetof(nf_box,eps_s), offsetof(nf_box,pos), offsetof(nf_box,off),"
         "offsetof(nf_box,cell_start), offsetof(nf_box,order), offsetof(nf_box,nbad));return 0;}\n")
     exe = tmp_path / "layout"
@@ -64,7 +64,7 @@ def test_struct_layout_matches_header(lib, tmp_path):
                                           check=True).stdout.split()]
     B = lib.NfBox
     want = [ctypes.sizeof(B)] + [getattr(B, f).offset for f in
-                                 ("n", "K", "reserved", "L", "eps_s", "pos", "off", "cell_start",
+                                 ("n", "K", "dense_min", "L", "eps_s", "pos", "off", "cell_start",
                                   "order", "nbad")]
     assert got == want
 
@@ -84,6 +84,8 @@ def test_workspace_bytes_and_validation(lib):
         _box(lib, L=float("inf")),
         _box(lib, eps=0.0),
         _box(lib, eps=float("nan")),
+        lib.NfBox(10, 8, 1, 1.0, 0.01, 0x1000, 0x1000, 0x1000, 0x1000, None),   # dense_min 1
+        lib.NfBox(10, 8, 66, 1.0, 0.01, 0x1000, 0x1000, 0x1000, 0x1000, None),  # dense_min 66
         lib.NfBox(10, 8, 0, 1.0, 0.01, 0x1000, 0, 0x1000, 0x1000, None),   # off NULL
         lib.NfBox(0, 8, 0, 1.0, 0.01, 0, 0, 0, 0, None),                    # cell_start NULL
     ]
