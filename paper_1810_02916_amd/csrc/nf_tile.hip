@@ -11,13 +11,14 @@
 //               as SGPR operands, and the sink is shifted into each source
 //               cell's frame.  No LDS, so many waves fit on a CU and hide the
 //               load latency.  Items run heaviest neighbourhood first.
-//   * light  -- all sinks of a cell holding fewer particles (at most 64).  The 125 source
+//   * light  -- all sinks of a cell holding fewer particles (at most 64), one
+//               item per 4-wave workgroup.  The 125 source
 //               cells are staged in LDS in the sink cell's own frame,
 //               (o_x + dx, o_y + dy, o_z + dz), the 27 cells with |d| <= 1
 //               first, then the 98 outer cells, so the sum is two contiguous
-//               segments; the g sinks are spread over the wave as (sink a,
-//               source slice b), lane = a + g b, P = 64 / g slices, summed at
-//               the end in a fixed order.
+//               segments; the g sinks are spread over the 256 threads as
+//               (sink a, source slice b), thread = a + g b, P = 256 / g
+//               slices, summed at the end by a fixed-order pairwise tree.
 // In both paths a source of the sink's own cell is used unshifted, so the
 // closest pairs are formed from the exact float offsets, and a cell of the
 // outer shell of the block (some |d| = 2) is at r >= 1 and takes the Newton
@@ -30,6 +31,8 @@ namespace nf {
 namespace {
 
 constexpr int kUnit = 64;            // sinks per wave
+constexpr int kLightWaves = 4;       // waves sharing one light item
+constexpr int kLightThreads = 64 * kLightWaves;
 constexpr int kRows = 25;            // (dx, dy) rows of the 5x5x5 block
 constexpr float kTinyT = 1.0e-30f;   // floor on r^2: a coincident pair gives 0
 constexpr int kFlush = 32;           // compensated mode: plain partials of <= 32 terms
@@ -350,8 +353,9 @@ struct LightSmem {
     int pg[kPiece];                  // global start of the piece
     float pb[kPiece];                // z shift minus the source's cell index
     int cnt[2][kRows];               // per row: inner-part and outer-part counts
-    float red[3][kUnit];
+    float red[6][kLightThreads];     // slice partials (sum, compensation) per component
     int item;
+    int next;
     int inner;                       // staged particles of the 27 inner cells
     int total;
 };
@@ -410,19 +414,21 @@ __device__ __forceinline__ void segment(const float4 *__restrict__ sx, const flo
 }
 
 template <int MODE, bool COMP, int CAP>
-__global__ void __launch_bounds__(kUnit)
+__global__ void __launch_bounds__(kLightThreads)
 k_light(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
         const uint32_t *__restrict__ totals, uint32_t *counter,
         const float4 *__restrict__ cot_sorted) {
     __shared__ LightSmem<MODE, CAP> sm;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x;   // 0 .. kLightThreads-1, all waves share the item
     const int nitems = (int)totals[1];
 
+    if (lane == 0) sm.item = (int)atomicAdd(counter, 1u);
     for (;;) {
-        if (lane == 0) sm.item = (int)atomicAdd(counter, 1u);
         __syncthreads();
         const int itx = uni(sm.item);
         if (itx >= nitems) break;
+        // claim the next item now; the atomic completes while this one runs
+        if (lane == 0) sm.next = (int)atomicAdd(counter, 1u);
         const Item I = items[itx];
         const DevBox &B = boxes[I.box];
         const int K = B.K;
@@ -519,25 +525,60 @@ k_light(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
         const int inner = uni(sm.inner);
         const bool single = total <= CAP;
 
-        // stage the union window [u0, u1)
+        // stage the union window [u0, u1): wave w takes rows w, w+4, ... in chunks
+        // of 64 elements; the loads of four chunks are issued before any store
         auto stage = [&](int u0, int u1) {
-            for (int pc = 0; pc < kPiece; ++pc) {
-                const int pu = uni(sm.pu[pc]);
-                const int a = max(pu, u0), e = min(pu + uni(sm.pn[pc]), u1);
-                if (a >= e) continue;
-                const int gshift = uni(sm.pg[pc]) - pu;
-                const int r = pc / kSlots;
-                const float dxf = (float)(r / 5 - 2), dyf = (float)(r % 5 - 2);
-                const float bias = sm.pb[pc];
-                for (int v = a + lane; v < e; v += kUnit) {
-                    const float4 o = off[v + gshift];
-                    float4 t = make_float4(o.x + dxf, o.y + dyf, o.z + (o.w + bias), 0.f);
-                    if constexpr (MODE == 1) {
-                        const float4 c = cot_sorted[B.base + v + gshift];
-                        t.w = c.x;
-                        sm.sv[v - u0] = make_float2(c.y, c.z);
+            const int wv = lane >> 6, ln = lane & 63;
+            int r = wv, c = 0;
+            while (r < kRows) {
+                float4 buf[4];
+                float4 cbuf[4];
+                int dst[4];
+                float fx[4], fy[4], fb[4];
+                bool ok[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    ok[t] = false;
+                    if (r < kRows) {
+                        const int n0 = uni(sm.pn[r * kSlots]), n1 = uni(sm.pn[r * kSlots + 1]),
+                                  n2 = uni(sm.pn[r * kSlots + 2]), n3 = uni(sm.pn[r * kSlots + 3]);
+                        const int len = n0 + n1 + n2 + n3;
+                        const int l = 64 * c + ln;
+                        if (l < len) {
+                            const int q = (l >= n0) + (l >= n0 + n1) + (l >= n0 + n1 + n2);
+                            const int base = q == 0 ? 0 : q == 1 ? n0 : q == 2 ? n0 + n1 : n0 + n1 + n2;
+                            const int e = l - base;
+                            const int d = sm.pu[r * kSlots + q] + e;
+                            if (d >= u0 && d < u1) {
+                                const int gsrc = sm.pg[r * kSlots + q] + e;
+                                buf[t] = off[gsrc];
+                                if constexpr (MODE == 1) cbuf[t] = cot_sorted[B.base + gsrc];
+                                dst[t] = d - u0;
+                                fx[t] = (float)(r / 5 - 2);
+                                fy[t] = (float)(r % 5 - 2);
+                                fb[t] = sm.pb[r * kSlots + q];
+                                ok[t] = true;
+                            }
+                        }
+                        if (64 * (c + 1) < len) {
+                            ++c;
+                        } else {
+                            c = 0;
+                            r += kLightWaves;
+                        }
                     }
-                    sm.sx[v - u0] = t;
+                }
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    if (ok[t]) {
+                        const float4 o = buf[t];
+                        float4 v = make_float4(o.x + fx[t], o.y + fy[t], o.z + (o.w + fb[t]), 0.f);
+                        if constexpr (MODE == 1) {
+                            v.w = cbuf[t].x;
+                            sm.sv[dst[t]] = make_float2(cbuf[t].y, cbuf[t].z);
+                        }
+                        sm.sx[dst[t]] = v;
+                    }
                 }
             }
             __syncthreads();
@@ -547,7 +588,7 @@ k_light(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
 
         const Coef k{B.cA, B.cB, B.cC, 2.0f * B.cC, B.eps * B.eps};
         const bool fast = B.outer_newton != 0;
-        const int P = kUnit / g;
+        const int P = kLightThreads / g;
         const bool active = lane < g * P;
         const int a = active ? lane % g : 0;
         const int b = active ? lane / g : 0;
@@ -572,31 +613,64 @@ k_light(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
                                                k, acc);
             }
         }
-        // ---- fixed-order sum over slices
-        float3 f = value<COMP>(acc);
-        sm.red[0][lane] = f.x;
-        sm.red[1][lane] = f.y;
-        sm.red[2][lane] = f.z;
-        __syncthreads();
-        if (lane < g) {
-            Acc t;
-            for (int sl = 0; sl < P; ++sl)
-                fold<COMP>(t, sm.red[0][lane + sl * g], sm.red[1][lane + sl * g],
-                           sm.red[2][lane + sl * g]);
-            store(B, s0 + lane, value<COMP>(t));
+        // ---- fixed-order pairwise sum over slices: slice b adds slice b + half
+        //      (TwoSum-compensated in the compensated mode)
+        if constexpr (COMP) {
+            sm.red[0][lane] = acc.x;
+            sm.red[1][lane] = acc.y;
+            sm.red[2][lane] = acc.z;
+            sm.red[3][lane] = -acc.cx;
+            sm.red[4][lane] = -acc.cy;
+            sm.red[5][lane] = -acc.cz;
+        } else {
+            sm.red[0][lane] = acc.x;
+            sm.red[1][lane] = acc.y;
+            sm.red[2][lane] = acc.z;
         }
         __syncthreads();
+        for (int span = P; span > 1;) {
+            const int half = (span + 1) >> 1;
+            if (active && b < span - half) {
+                const int o = lane + half * g;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    if constexpr (COMP) {
+                        const float x = sm.red[c][lane], y = sm.red[c][o];
+                        const float t = x + y;
+                        const float yp = t - x;
+                        const float e = (x - (t - yp)) + (y - yp);
+                        sm.red[c][lane] = t;
+                        sm.red[c + 3][lane] = sm.red[c + 3][lane] + sm.red[c + 3][o] + e;
+                    } else {
+                        sm.red[c][lane] = sm.red[c][lane] + sm.red[c][o];
+                    }
+                }
+            }
+            __syncthreads();
+            span = half;
+        }
+        if (lane < g) {
+            float3 f;
+            if constexpr (COMP)
+                f = make_float3(sm.red[0][lane] + sm.red[3][lane], sm.red[1][lane] + sm.red[4][lane],
+                                sm.red[2][lane] + sm.red[5][lane]);
+            else
+                f = make_float3(sm.red[0][lane], sm.red[1][lane], sm.red[2][lane]);
+            store(B, s0 + lane, f);
+        }
+        __syncthreads();
+        if (lane == 0) sm.item = sm.next;
     }
 }
 
 // ------------------------------------------------------------------ launches
 
 template <typename Kern>
-int persistent_grid(Kern kern) {
+int persistent_grid(Kern kern, int threads) {
     int dev = 0, ncu = 0, per = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, kUnit, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, threads, 0);
     return std::max(1, ncu) * std::max(1, per);
 }
 
@@ -604,13 +678,13 @@ template <int MODE, bool COMP>
 hipError_t launch_force(const DevBox *d_boxes, const TilePlan &tp, const float4 *cot,
                         hipStream_t s) {
     constexpr int CAP = MODE == 0 ? 1024 : 768;
-    static const int gd = persistent_grid(k_dense<MODE, COMP>);
-    static const int gl = persistent_grid(k_light<MODE, COMP, CAP>);
+    static const int gd = persistent_grid(k_dense<MODE, COMP>, kUnit);
+    static const int gl = persistent_grid(k_light<MODE, COMP, CAP>, kLightThreads);
     hipLaunchKernelGGL((k_dense<MODE, COMP>), dim3(gd), dim3(kUnit), 0, s, d_boxes,
                        (const Item *)tp.dense, (const uint32_t *)tp.totals, tp.counter, cot);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_light<MODE, COMP, CAP>), dim3(gl), dim3(kUnit), 0, s, d_boxes,
+    hipLaunchKernelGGL((k_light<MODE, COMP, CAP>), dim3(gl), dim3(kLightThreads), 0, s, d_boxes,
                        (const Item *)tp.light, (const uint32_t *)tp.totals, tp.counter + 1, cot);
     return hipGetLastError();
 }
