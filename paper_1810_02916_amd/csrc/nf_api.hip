@@ -87,8 +87,8 @@ struct Layout {
     size_t table_off = 0, table_bytes = 0;
     size_t keys_off[2] = {0, 0}, vals_off[2] = {0, 0};
     size_t hist_off = 0, cellcnt_off = 0, scan_off = 0;
-    size_t cot_off = 0, lcnt_off = 0, bucket_off = 0, totals_off = 0, dense_off = 0,
-           light_off = 0, counter_off = 0, fscan_off = 0;
+    size_t cot_off = 0, cellinfo_off = 0, bucket_off = 0, totals_off = 0, dense_off = 0,
+           light_off = 0, counter_off = 0;
     int64_t max_dense = 0;
     size_t total = 0;
     int64_t nblk = 0;
@@ -159,8 +159,8 @@ int validate(int nbox, const nf_box *boxes, Layout &L) {
     o = scratch0;
     L.cot_off = o;
     o = align_up(o + 16 * (size_t)L.N, 256);
-    L.lcnt_off = o;
-    o = align_up(o + 4 * (size_t)(L.C + 1), 256);
+    L.cellinfo_off = o;
+    o = align_up(o + 4 * (size_t)L.C, 256);
     L.bucket_off = o;
     o = align_up(o + 4 * 2 * (size_t)plan_buckets(), 256);
     L.totals_off = o;
@@ -172,9 +172,7 @@ int validate(int nbox, const nf_box *boxes, Layout &L) {
     L.light_off = o;
     o = align_up(o + sizeof(Item) * (size_t)(L.C + 16), 256);
     L.counter_off = o;
-    o = align_up(o + 8, 256);
-    L.fscan_off = o;
-    o = align_up(o + 4 * (size_t)scan_scratch_words(L.C + 1), 256);
+    o = align_up(o + 4 * (size_t)queue_words(), 256);
     L.total = std::max(bin_end, o);
     return NF_OK;
 }
@@ -329,14 +327,13 @@ static int force_common(int nbox, const nf_box *boxes, double gm, uint32_t flags
         TilePlan tp;
         tp.TG = L.C;
         tp.max_cells = L.max_ncell;
-        tp.lcnt = reinterpret_cast<uint32_t *>(w + L.lcnt_off);
+        tp.cellinfo = reinterpret_cast<uint32_t *>(w + L.cellinfo_off);
         tp.bucket_cnt = reinterpret_cast<uint32_t *>(w + L.bucket_off);
         tp.bucket_off = tp.bucket_cnt + plan_buckets();
         tp.totals = reinterpret_cast<uint32_t *>(w + L.totals_off);
         tp.dense = reinterpret_cast<Item *>(w + L.dense_off);
         tp.light = reinterpret_cast<Item *>(w + L.light_off);
         tp.counter = reinterpret_cast<uint32_t *>(w + L.counter_off);
-        tp.scan_scratch = reinterpret_cast<uint32_t *>(w + L.fscan_off);
         e = vjp ? gather_cot_launch(d_tab, nbox, p, s) : hipSuccess;
         if (e == hipSuccess) e = plan_launch(d_tab, nbox, tp, s);
         if (e == hipSuccess)

@@ -33,16 +33,16 @@ hipError_t bin_launch(const DevBox *d_boxes, int nbox, const BinPlan &p, hipStre
 struct TilePlan {
     int64_t TG = 0;              // cells over all boxes (planning is per cell)
     int64_t max_cells = 0;       // largest per-box cell count
-    uint32_t *lcnt = nullptr;    // [TG + 1] light items per cell -> exclusive scan
-    uint32_t *bucket_cnt = nullptr;   // [plan_buckets()] dense items per cost bucket
-    uint32_t *bucket_off = nullptr;   // [plan_buckets()] first dense item of each bucket
+    uint32_t *cellinfo = nullptr;     // [TG] item kind and cost bucket per cell
+    uint32_t *bucket_cnt = nullptr;   // [plan_buckets()] items per (kind, cost bucket)
+    uint32_t *bucket_off = nullptr;   // [plan_buckets()] first item of each bucket
     uint32_t *totals = nullptr;  // [2] dense and light item counts
     Item *dense = nullptr;       // dense items, heaviest first
-    Item *light = nullptr;       // light items, cell order
-    uint32_t *counter = nullptr; // [2] queue counters
-    uint32_t *scan_scratch = nullptr;
+    Item *light = nullptr;       // light items, heaviest first
+    uint32_t *counter = nullptr; // [queue_words()] queue counters
 };
 int plan_buckets();
+int queue_words();
 hipError_t plan_launch(const DevBox *d_boxes, int nbox, const TilePlan &tp, hipStream_t s);
 // mode 0: accelerations, 1: VJP (cot = cotangents in sorted order)
 hipError_t tile_launch(const DevBox *d_boxes, int mode, bool compensated, const TilePlan &tp,

@@ -31,6 +31,8 @@ namespace nf {
 namespace {
 
 constexpr int kUnit = 64;            // sinks per wave
+constexpr int kQueues = 32;          // light-item queues (a multiple of the 8 XCDs)
+constexpr int kQueueStride = 32;     // words between queue counters (own 128-byte line)
 constexpr int kLightWaves = 4;       // waves sharing one light item
 constexpr int kLightThreads = 64 * kLightWaves;
 constexpr int kRows = 25;            // (dx, dy) rows of the 5x5x5 block
@@ -58,66 +60,98 @@ __device__ int block_sources(const int32_t *cs, int K, int cx, int cy, int cz) {
     return s;
 }
 
-// Cost bucket of a dense cell: quarter octaves of its block's source count.
+// Cost buckets: quarter octaves of a pair count.  A dense item (64 sinks)
+// costs in proportion to its block's source count S, a light item to g * S.
 constexpr int kBuckets = 128;
-__device__ __forceinline__ int cost_bucket(int sources) {
-    const float l = __log2f((float)max(sources, 1));
+constexpr int kKinds = 2;                  // 0: dense, 1: light
+constexpr uint32_t kEmptyCell = 0xffffffffu;
+__device__ __forceinline__ int cost_bucket(float pairs) {
+    const float l = __log2f(fmaxf(pairs, 1.0f));
     return min(kBuckets - 1, (int)(4.0f * l));
 }
 
-// Per cell: light cells (1 .. dense_min-1 particles) count one light item; dense cells
-// add their ceil(n / 64) chunks to their cost bucket.
+// Per cell: the kind and cost bucket of its items (cellinfo = kind << 16 | bucket,
+// kEmptyCell for an empty cell), and the item counts per (kind, bucket), summed
+// in LDS first so that each block adds one value per non-empty bucket.
 __global__ void __launch_bounds__(256)
-k_plan_count(const DevBox *boxes, uint32_t *lcnt, uint32_t *bucket_cnt) {
+k_plan_count(const DevBox *boxes, uint32_t *cellinfo, uint32_t *bucket_cnt) {
+    __shared__ uint32_t h[kKinds * kBuckets];
+    for (int t = threadIdx.x; t < kKinds * kBuckets; t += 256) h[t] = 0;
+    __syncthreads();
     const DevBox &B = boxes[blockIdx.y];
     const int c = blockIdx.x * 256 + threadIdx.x;
-    if (c >= B.ncell) return;
-    const int n = B.cell_start[c + 1] - B.cell_start[c];
-    lcnt[B.cellbase + c] = (n > 0 && n < B.dense_min) ? 1u : 0u;
-    if (n >= B.dense_min) {
-        const int K = B.K;
-        const int b = cost_bucket(block_sources(B.cell_start, K, c / (K * K), (c / K) % K, c % K));
-        atomicAdd(&bucket_cnt[b], (uint32_t)((n + kUnit - 1) / kUnit));
+    if (c < B.ncell) {
+        const int n = B.cell_start[c + 1] - B.cell_start[c];
+        uint32_t info = kEmptyCell;
+        if (n > 0) {
+            const int K = B.K;
+            const float S = (float)block_sources(B.cell_start, K, c / (K * K), (c / K) % K, c % K);
+            if (n >= B.dense_min) {
+                const int b = cost_bucket(S);
+                atomicAdd(&h[b], (uint32_t)((n + kUnit - 1) / kUnit));
+                info = (uint32_t)b;
+            } else {
+                const int b = cost_bucket((float)n * S);
+                atomicAdd(&h[kBuckets + b], 1u);
+                info = (1u << 16) | (uint32_t)b;
+            }
+        }
+        cellinfo[B.cellbase + c] = info;
     }
+    __syncthreads();
+    for (int t = threadIdx.x; t < kKinds * kBuckets; t += 256)
+        if (h[t]) atomicAdd(&bucket_cnt[t], h[t]);
 }
 
-// Bucket offsets, heaviest bucket first; totals[0] = dense items,
-// totals[1] = light items (from the scanned light counts).
-__global__ void __launch_bounds__(kBuckets)
-k_plan_buckets(uint32_t *bucket_cnt, uint32_t *bucket_off, const uint32_t *__restrict__ lscan,
-               int64_t C, uint32_t *totals) {
-    __shared__ uint32_t c[kBuckets];
+// Bucket offsets per kind, heaviest bucket first; totals[kind] = item count.
+__global__ void __launch_bounds__(kKinds * kBuckets)
+k_plan_buckets(uint32_t *bucket_cnt, uint32_t *bucket_off, uint32_t *totals) {
+    __shared__ uint32_t c[kKinds * kBuckets];
     const int t = threadIdx.x;
+    const int kind = t / kBuckets, bk = t % kBuckets;
     c[t] = bucket_cnt[t];
     __syncthreads();
     uint32_t off = 0;
-    for (int b = kBuckets - 1; b > t; --b) off += c[b];
+    for (int b = kBuckets - 1; b > bk; --b) off += c[kind * kBuckets + b];
     bucket_off[t] = off;
     bucket_cnt[t] = 0;   // reused as the fill cursor by k_plan_emit
-    if (t == 0) {
-        uint32_t tot = 0;
-        for (int b = 0; b < kBuckets; ++b) tot += c[b];
-        totals[0] = tot;
-        totals[1] = lscan[C];
-    }
+    if (bk == 0) totals[kind] = off + c[t];
 }
 
+// Items into their bucket ranges: each block reserves one range per non-empty
+// bucket with a global atomic and places its cells by LDS ranks.  The order
+// inside a bucket depends on timing; every item's result does not.
 __global__ void __launch_bounds__(256)
-k_plan_emit(const DevBox *boxes, const uint32_t *__restrict__ lscan,
+k_plan_emit(const DevBox *boxes, const uint32_t *__restrict__ cellinfo,
             const uint32_t *__restrict__ bucket_off, uint32_t *bucket_cur, Item *dense,
             Item *light) {
+    __shared__ uint32_t h[kKinds * kBuckets];
+    __shared__ uint32_t base[kKinds * kBuckets];
+    for (int t = threadIdx.x; t < kKinds * kBuckets; t += 256) h[t] = 0;
+    __syncthreads();
     const DevBox &B = boxes[blockIdx.y];
     const int c = blockIdx.x * 256 + threadIdx.x;
-    if (c >= B.ncell) return;
-    const int n = B.cell_start[c + 1] - B.cell_start[c];
-    if (n >= B.dense_min) {
-        const int K = B.K;
-        const int b = cost_bucket(block_sources(B.cell_start, K, c / (K * K), (c / K) % K, c % K));
+    uint32_t info = kEmptyCell, slot = 0, rank = 0;
+    int n = 0;
+    if (c < B.ncell) {
+        info = cellinfo[B.cellbase + c];
+        if (info != kEmptyCell) {
+            n = B.cell_start[c + 1] - B.cell_start[c];
+            slot = (info >> 16) * kBuckets + (info & 0xffffu);
+            rank = atomicAdd(&h[slot], info >> 16 ? 1u : (uint32_t)((n + kUnit - 1) / kUnit));
+        }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < kKinds * kBuckets; t += 256)
+        if (h[t]) base[t] = bucket_off[t] + atomicAdd(&bucket_cur[t], h[t]);
+    __syncthreads();
+    if (info == kEmptyCell) return;
+    const uint32_t at = base[slot] + rank;
+    if (info >> 16) {
+        light[at] = Item{(int)blockIdx.y, c, 1, 0};
+    } else {
         const int nch = (n + kUnit - 1) / kUnit;
-        Item *o = dense + bucket_off[b] + atomicAdd(&bucket_cur[b], (uint32_t)nch);
-        for (int k = 0; k < nch; ++k) o[k] = Item{(int)blockIdx.y, c, 1, k};
-    } else if (n > 0) {
-        light[lscan[B.cellbase + c]] = Item{(int)blockIdx.y, c, 1, 0};
+        for (int k = 0; k < nch; ++k) dense[at + k] = Item{(int)blockIdx.y, c, 1, k};
     }
 }
 
@@ -422,13 +456,18 @@ k_light(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
     const int lane = threadIdx.x;   // 0 .. kLightThreads-1, all waves share the item
     const int nitems = (int)totals[1];
 
-    if (lane == 0) sm.item = (int)atomicAdd(counter, 1u);
+    // kQueues interleaved queues: workgroup w draws from queue q = w % kQueues,
+    // whose k-th claim is item k * kQueues + q.  A single counter would cap
+    // the item rate at what one address sustains for atomics.
+    const int q = (int)(blockIdx.x % kQueues);
+    uint32_t *qc = counter + kQueueStride * q;
+    if (lane == 0) sm.item = (int)atomicAdd(qc, 1u) * kQueues + q;
     for (;;) {
         __syncthreads();
         const int itx = uni(sm.item);
         if (itx >= nitems) break;
         // claim the next item now; the atomic completes while this one runs
-        if (lane == 0) sm.next = (int)atomicAdd(counter, 1u);
+        if (lane == 0) sm.next = (int)atomicAdd(qc, 1u) * kQueues + q;
         const Item I = items[itx];
         const DevBox &B = boxes[I.box];
         const int K = B.K;
@@ -679,39 +718,43 @@ hipError_t launch_force(const DevBox *d_boxes, const TilePlan &tp, const float4 
                         hipStream_t s) {
     constexpr int CAP = MODE == 0 ? 1024 : 768;
     static const int gd = persistent_grid(k_dense<MODE, COMP>, kUnit);
-    static const int gl = persistent_grid(k_light<MODE, COMP, CAP>, kLightThreads);
+    // every queue needs at least one workgroup: the grid is a multiple of kQueues
+    static const int gl =
+        (persistent_grid(k_light<MODE, COMP, CAP>, kLightThreads) + kQueues - 1) / kQueues *
+        kQueues;
     hipLaunchKernelGGL((k_dense<MODE, COMP>), dim3(gd), dim3(kUnit), 0, s, d_boxes,
                        (const Item *)tp.dense, (const uint32_t *)tp.totals, tp.counter, cot);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_light<MODE, COMP, CAP>), dim3(gl), dim3(kLightThreads), 0, s, d_boxes,
-                       (const Item *)tp.light, (const uint32_t *)tp.totals, tp.counter + 1, cot);
+                       (const Item *)tp.light, (const uint32_t *)tp.totals,
+                       tp.counter + kQueueStride, cot);
     return hipGetLastError();
 }
 
 }  // namespace
 
-int plan_buckets() { return kBuckets; }
+int plan_buckets() { return kKinds * kBuckets; }
+int queue_words() { return (1 + kQueues) * kQueueStride; }
 
 hipError_t plan_launch(const DevBox *d_boxes, int nbox, const TilePlan &tp, hipStream_t s) {
     hipError_t e;
     dim3 grid((unsigned)((tp.max_cells + 255) / 256), (unsigned)nbox);
-    if ((e = fill_u32(tp.lcnt + tp.TG, 1, 0u, s)) != hipSuccess) return e;
-    if ((e = fill_u32(tp.bucket_cnt, kBuckets, 0u, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_plan_count, grid, dim3(256), 0, s, d_boxes, tp.lcnt, tp.bucket_cnt);
+    if ((e = fill_u32(tp.bucket_cnt, kKinds * kBuckets, 0u, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_plan_count, grid, dim3(256), 0, s, d_boxes, tp.cellinfo, tp.bucket_cnt);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = scan_exclusive(tp.lcnt, tp.TG + 1, tp.scan_scratch, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_plan_buckets, dim3(1), dim3(kBuckets), 0, s, tp.bucket_cnt,
-                       tp.bucket_off, (const uint32_t *)tp.lcnt, tp.TG, tp.totals);
+    hipLaunchKernelGGL(k_plan_buckets, dim3(1), dim3(kKinds * kBuckets), 0, s, tp.bucket_cnt,
+                       tp.bucket_off, tp.totals);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_plan_emit, grid, dim3(256), 0, s, d_boxes, (const uint32_t *)tp.lcnt,
-                       (const uint32_t *)tp.bucket_off, tp.bucket_cnt, tp.dense, tp.light);
+    hipLaunchKernelGGL(k_plan_emit, grid, dim3(256), 0, s, d_boxes,
+                       (const uint32_t *)tp.cellinfo, (const uint32_t *)tp.bucket_off,
+                       tp.bucket_cnt, tp.dense, tp.light);
     return hipGetLastError();
 }
 
 hipError_t tile_launch(const DevBox *d_boxes, int mode, bool compensated, const TilePlan &tp,
                        const float4 *cot, hipStream_t s) {
-    hipError_t e = fill_u32(tp.counter, 2, 0u, s);
+    hipError_t e = fill_u32(tp.counter, queue_words(), 0u, s);
     if (e != hipSuccess) return e;
     if (mode == 0)
         return compensated ? launch_force<0, true>(d_boxes, tp, cot, s)
