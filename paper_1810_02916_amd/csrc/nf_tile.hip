@@ -382,11 +382,9 @@ template <int MODE, int CAP>
 struct LightSmem {
     float4 sx[CAP];                  // (o_x + dx, o_y + dy, o_z + dz, v_x)
     float2 sv[MODE == 1 ? CAP : 1];  // (v_y, v_z) for the VJP
-    int pu[kPiece];                  // staged start of each piece
-    int pn[kPiece];                  // particles in the piece
-    int pg[kPiece];                  // global start of the piece
-    float pb[kPiece];                // z shift minus the source's cell index
-    int cnt[2][kRows];               // per row: inner-part and outer-part counts
+    int rs[128];                     // staged start of each non-empty piece (run), ascending
+    float4 rd[kPiece];               // per run: (global minus staged index, dx, dy, z bias)
+    int nrun;
     float red[6][kLightThreads];     // slice partials (sum, compensation) per component
     int item;
     int next;
@@ -448,10 +446,11 @@ __device__ __forceinline__ void segment(const float4 *__restrict__ sx, const flo
 }
 
 template <int MODE, bool COMP, int CAP>
-__global__ void __launch_bounds__(kLightThreads)
+__global__ void __launch_bounds__(kLightThreads) __attribute__((amdgpu_waves_per_eu(6)))
 k_light(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
         const uint32_t *__restrict__ totals, uint32_t *counter,
         const float4 *__restrict__ cot_sorted) {
+    static_assert(CAP % kLightThreads == 0, "a staging window is whole rounds of the workgroup");
     __shared__ LightSmem<MODE, CAP> sm;
     const int lane = threadIdx.x;   // 0 .. kLightThreads-1, all waves share the item
     const int nitems = (int)totals[1];
@@ -477,86 +476,97 @@ k_light(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
         const int s0 = uni(cs[I.cell0]);
         const int g = uni(cs[I.cell0 + 1]) - s0;
 
-        // ---- pieces, one lane per row
-        if (lane < kRows) {
+        // ---- pieces and run table: wave 0, one lane per row.  Staged layout: the
+        //      inner parts of rows 0..24, then their outer parts; the non-empty
+        //      pieces in that order are the runs.
+        if (lane < 64) {
             const int r = lane;
-            const int dx = r / 5 - 2, dy = r % 5 - 2;
-            const bool in_row = dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1;
-            const int rb = (wrapk(cx + dx, K) * K + wrapk(cy + dy, K)) * K;
-            int pg[kSlots], pn[kSlots];
-            float pb[kSlots];
-            // a run of z cells [za, zb] relative to the sink (za <= zb), split at the wrap
-            auto run = [&](int q, int za, int zb) {
-                const int lo = z + za, hi = z + zb;
-                if (lo < 0) {   // [lo+K, K-1] then [0, hi]
-                    pg[q] = cs[rb + lo + K];
-                    pn[q] = cs[rb + K] - pg[q];
-                    pb[q] = -(float)(z + K);
-                    pg[q + 1] = cs[rb];
-                    pn[q + 1] = cs[rb + hi + 1] - pg[q + 1];
-                    pb[q + 1] = -(float)z;
-                } else if (hi >= K) {   // [lo, K-1] then [0, hi-K]
-                    pg[q] = cs[rb + lo];
-                    pn[q] = cs[rb + K] - pg[q];
-                    pb[q] = -(float)z;
-                    pg[q + 1] = cs[rb];
-                    pn[q + 1] = cs[rb + hi - K + 1] - pg[q + 1];
-                    pb[q + 1] = (float)(K - z);
+            int pg[kSlots] = {0, 0, 0, 0}, pn[kSlots] = {0, 0, 0, 0};
+            float pb[kSlots] = {0.f, 0.f, 0.f, 0.f};
+            if (r < kRows) {
+                const int dx = r / 5 - 2, dy = r % 5 - 2;
+                const bool in_row = dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1;
+                const int rb = (wrapk(cx + dx, K) * K + wrapk(cy + dy, K)) * K;
+                // a run of z cells [za, zb] relative to the sink (za <= zb), split at the wrap
+                auto run = [&](int q, int za, int zb) {
+                    const int lo = z + za, hi = z + zb;
+                    if (lo < 0) {   // [lo+K, K-1] then [0, hi]
+                        pg[q] = cs[rb + lo + K];
+                        pn[q] = cs[rb + K] - pg[q];
+                        pb[q] = -(float)(z + K);
+                        pg[q + 1] = cs[rb];
+                        pn[q + 1] = cs[rb + hi + 1] - pg[q + 1];
+                        pb[q + 1] = -(float)z;
+                    } else if (hi >= K) {   // [lo, K-1] then [0, hi-K]
+                        pg[q] = cs[rb + lo];
+                        pn[q] = cs[rb + K] - pg[q];
+                        pb[q] = -(float)z;
+                        pg[q + 1] = cs[rb];
+                        pn[q + 1] = cs[rb + hi - K + 1] - pg[q + 1];
+                        pb[q + 1] = (float)(K - z);
+                    } else {
+                        pg[q] = cs[rb + lo];
+                        pn[q] = cs[rb + hi + 1] - pg[q];
+                        pb[q] = -(float)z;
+                    }
+                };
+                if (in_row) {
+                    run(0, -1, 1);
+                    // the two single cells at dz = -2 and dz = +2
+                    const int zm = z - 2, zp = z + 2;
+                    const int cm = rb + wrapk(zm, K), cp = rb + wrapk(zp, K);
+                    pg[2] = cs[cm];
+                    pn[2] = cs[cm + 1] - pg[2];
+                    pb[2] = -(float)z + (zm < 0 ? -(float)K : 0.f);
+                    pg[3] = cs[cp];
+                    pn[3] = cs[cp + 1] - pg[3];
+                    pb[3] = -(float)z + (zp >= K ? (float)K : 0.f);
                 } else {
-                    pg[q] = cs[rb + lo];
-                    pn[q] = cs[rb + hi + 1] - pg[q];
-                    pb[q] = -(float)z;
-                    pg[q + 1] = 0;
-                    pn[q + 1] = 0;
-                    pb[q + 1] = 0.f;
+                    run(2, -2, 2);
                 }
-            };
-            if (in_row) {
-                run(0, -1, 1);
-                // the two single cells at dz = -2 and dz = +2
-                const int zm = z - 2, zp = z + 2;
-                const int cm = rb + wrapk(zm, K), cp = rb + wrapk(zp, K);
-                pg[2] = cs[cm];
-                pn[2] = cs[cm + 1] - pg[2];
-                pb[2] = -(float)z + (zm < 0 ? -(float)K : 0.f);
-                pg[3] = cs[cp];
-                pn[3] = cs[cp + 1] - pg[3];
-                pb[3] = -(float)z + (zp >= K ? (float)K : 0.f);
-            } else {
-                pg[0] = pg[1] = 0;
-                pn[0] = pn[1] = 0;
-                pb[0] = pb[1] = 0.f;
-                run(2, -2, 2);
             }
-            for (int q = 0; q < kSlots; ++q) {
-                sm.pn[r * kSlots + q] = pn[q];
-                sm.pg[r * kSlots + q] = pg[q];
-                sm.pb[r * kSlots + q] = pb[q];
-            }
-            sm.cnt[0][r] = pn[0] + pn[1];
-            sm.cnt[1][r] = pn[2] + pn[3];
-        }
-        __syncthreads();
-        if (lane < kRows) {
-            const int r = lane;
-            int in0 = 0, out0 = 0, tin = 0, tout = 0;
-            for (int q = 0; q < kRows; ++q) {
-                const int a = sm.cnt[0][q], e = sm.cnt[1][q];
-                if (q < r) {
-                    in0 += a;
-                    out0 += e;
+            // exclusive prefixes over rows of the inner and outer counts and of
+            // the non-empty piece counts (inner | outer << 16), by a wave scan
+            const int ca = pn[0] + pn[1], ce = pn[2] + pn[3];
+            const int cn = ((pn[0] > 0) + (pn[1] > 0)) | (((pn[2] > 0) + (pn[3] > 0)) << 16);
+            int ia = ca, ie = ce, in_ = cn;
+#pragma unroll
+            for (int o = 1; o < 32; o <<= 1) {
+                const int ta = __shfl_up(ia, o), te = __shfl_up(ie, o), tn = __shfl_up(in_, o);
+                if (r >= o) {
+                    ia += ta;
+                    ie += te;
+                    in_ += tn;
                 }
-                tin += a;
-                tout += e;
             }
-            out0 += tin;
-            sm.pu[r * kSlots + 0] = in0;
-            sm.pu[r * kSlots + 1] = in0 + sm.pn[r * kSlots + 0];
-            sm.pu[r * kSlots + 2] = out0;
-            sm.pu[r * kSlots + 3] = out0 + sm.pn[r * kSlots + 2];
+            const int tin = __shfl(ia, kRows - 1), tout = __shfl(ie, kRows - 1);
+            const int tn = __shfl(in_, kRows - 1);
+            const int kin = tn & 0xffff, kout = tn >> 16;
+            if (r < kRows) {
+                const int n0 = in_ - cn;
+                int start[kSlots], rank[kSlots];
+                start[0] = ia - ca;
+                start[1] = start[0] + pn[0];
+                start[2] = tin + (ie - ce);
+                start[3] = start[2] + pn[2];
+                rank[0] = n0 & 0xffff;
+                rank[1] = rank[0] + (pn[0] > 0);
+                rank[2] = kin + (n0 >> 16);
+                rank[3] = rank[2] + (pn[2] > 0);
+                const float dxf = (float)(r / 5 - 2), dyf = (float)(r % 5 - 2);
+#pragma unroll
+                for (int q = 0; q < kSlots; ++q) {
+                    if (pn[q] > 0) {
+                        sm.rs[rank[q]] = start[q];
+                        sm.rd[rank[q]] = make_float4(__int_as_float(pg[q] - start[q]), dxf, dyf,
+                                                     pb[q]);
+                    }
+                }
+            }
             if (r == 0) {
                 sm.inner = tin;
                 sm.total = tin + tout;
+                sm.nrun = kin + kout;
             }
         }
         __syncthreads();
@@ -564,60 +574,40 @@ k_light(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
         const int inner = uni(sm.inner);
         const bool single = total <= CAP;
 
-        // stage the union window [u0, u1): wave w takes rows w, w+4, ... in chunks
-        // of 64 elements; the loads of four chunks are issued before any store
+        // stage the union window [u0, u1): thread t takes elements u0 + t + 256 i,
+        // finds its run by a fixed 7-step binary search over the run starts,
+        // and issues all its loads before any LDS store
         auto stage = [&](int u0, int u1) {
-            const int wv = lane >> 6, ln = lane & 63;
-            int r = wv, c = 0;
-            while (r < kRows) {
-                float4 buf[4];
-                float4 cbuf[4];
-                int dst[4];
-                float fx[4], fy[4], fb[4];
-                bool ok[4];
+            constexpr int kPer = CAP / kLightThreads;
+            const int nrun = uni(sm.nrun);
+            float4 buf[kPer], cb[kPer], dsc[kPer];
+            int dl[kPer];
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    ok[t] = false;
-                    if (r < kRows) {
-                        const int n0 = uni(sm.pn[r * kSlots]), n1 = uni(sm.pn[r * kSlots + 1]),
-                                  n2 = uni(sm.pn[r * kSlots + 2]), n3 = uni(sm.pn[r * kSlots + 3]);
-                        const int len = n0 + n1 + n2 + n3;
-                        const int l = 64 * c + ln;
-                        if (l < len) {
-                            const int q = (l >= n0) + (l >= n0 + n1) + (l >= n0 + n1 + n2);
-                            const int base = q == 0 ? 0 : q == 1 ? n0 : q == 2 ? n0 + n1 : n0 + n1 + n2;
-                            const int e = l - base;
-                            const int d = sm.pu[r * kSlots + q] + e;
-                            if (d >= u0 && d < u1) {
-                                const int gsrc = sm.pg[r * kSlots + q] + e;
-                                buf[t] = off[gsrc];
-                                if constexpr (MODE == 1) cbuf[t] = cot_sorted[B.base + gsrc];
-                                dst[t] = d - u0;
-                                fx[t] = (float)(r / 5 - 2);
-                                fy[t] = (float)(r % 5 - 2);
-                                fb[t] = sm.pb[r * kSlots + q];
-                                ok[t] = true;
-                            }
-                        }
-                        if (64 * (c + 1) < len) {
-                            ++c;
-                        } else {
-                            c = 0;
-                            r += kLightWaves;
-                        }
-                    }
+            for (int i = 0; i < kPer; ++i) {
+                const int d = u0 + lane + kLightThreads * i;
+                dl[i] = d < u1 ? d - u0 : -1;
+                if (d < u1) {
+                    int pos = 0;
+#pragma unroll
+                    for (int st = 64; st > 0; st >>= 1)
+                        if (pos + st < nrun && sm.rs[pos + st] <= d) pos += st;
+                    dsc[i] = sm.rd[pos];
+                    const int gsrc = d + __float_as_int(dsc[i].x);
+                    buf[i] = off[gsrc];
+                    if constexpr (MODE == 1) cb[i] = cot_sorted[B.base + gsrc];
                 }
+            }
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    if (ok[t]) {
-                        const float4 o = buf[t];
-                        float4 v = make_float4(o.x + fx[t], o.y + fy[t], o.z + (o.w + fb[t]), 0.f);
-                        if constexpr (MODE == 1) {
-                            v.w = cbuf[t].x;
-                            sm.sv[dst[t]] = make_float2(cbuf[t].y, cbuf[t].z);
-                        }
-                        sm.sx[dst[t]] = v;
+            for (int i = 0; i < kPer; ++i) {
+                if (dl[i] >= 0) {
+                    const float4 o = buf[i];
+                    float4 v = make_float4(o.x + dsc[i].y, o.y + dsc[i].z, o.z + (o.w + dsc[i].w),
+                                           0.f);
+                    if constexpr (MODE == 1) {
+                        v.w = cb[i].x;
+                        sm.sv[dl[i]] = make_float2(cb[i].y, cb[i].z);
                     }
+                    sm.sx[dl[i]] = v;
                 }
             }
             __syncthreads();
