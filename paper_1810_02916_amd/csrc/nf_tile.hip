@@ -380,14 +380,16 @@ constexpr int kPiece = kRows * kSlots;
 
 template <int MODE, int CAP>
 struct LightSmem {
-    float4 sx[CAP];                  // (o_x + dx, o_y + dy, o_z + dz, v_x)
+    union {
+        float4 sx[CAP];                  // (o_x + dx, o_y + dy, o_z + dz, v_x)
+        float red[6][kLightThreads];     // after the sum: slice partials (sum, compensation)
+    };
     float2 sv[MODE == 1 ? CAP : 1];  // (v_y, v_z) for the VJP
     int rs[128];                     // staged start of each non-empty piece (run), ascending
     float4 rd[kPiece];               // per run: (global minus staged index, dx, dy, z bias)
     int nrun;
-    float red[6][kLightThreads];     // slice partials (sum, compensation) per component
-    int item;
-    int next;
+    int item;                        // current item and its (box, cell)
+    int ibox, icell;
     int inner;                       // staged particles of the 27 inner cells
     int total;
 };
@@ -460,21 +462,41 @@ k_light(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
     // the item rate at what one address sustains for atomics.
     const int q = (int)(blockIdx.x % kQueues);
     uint32_t *qc = counter + kQueueStride * q;
-    if (lane == 0) sm.item = (int)atomicAdd(qc, 1u) * kQueues + q;
+    if (lane == 0) {
+        const int first = (int)atomicAdd(qc, 1u) * kQueues + q;
+        sm.item = first;
+        if (first < nitems) {
+            sm.ibox = items[first].box;
+            sm.icell = items[first].cell0;
+        }
+    }
     for (;;) {
         __syncthreads();
         const int itx = uni(sm.item);
         if (itx >= nitems) break;
-        // claim the next item now; the atomic completes while this one runs
-        if (lane == 0) sm.next = (int)atomicAdd(qc, 1u) * kQueues + q;
-        const Item I = items[itx];
-        const DevBox &B = boxes[I.box];
+        const int ibox = uni(sm.ibox), cell0 = uni(sm.icell);
+        // claim the next item now (lane 0); its record is fetched once the setup
+        // below is done, and both complete while this item runs
+        int nxt = 0;
+        if (lane == 0) nxt = (int)atomicAdd(qc, 1u) * kQueues + q;
+        const DevBox &B = boxes[ibox];
         const int K = B.K;
-        const int cx = I.cell0 / (K * K), cy = (I.cell0 / K) % K, z = I.cell0 % K;
+        const int cx = cell0 / (K * K), cy = (cell0 / K) % K, z = cell0 % K;
         const int32_t *__restrict__ cs = B.cell_start;
         const float4 *__restrict__ off = B.off;
-        const int s0 = uni(cs[I.cell0]);
-        const int g = uni(cs[I.cell0 + 1]) - s0;
+        const int s0 = uni(cs[cell0]);
+        const int g = uni(cs[cell0 + 1]) - s0;
+
+        // ---- this lane's sink (sink a, source slice b), loaded before the setup
+        const Coef k{B.cA, B.cB, B.cC, 2.0f * B.cC, B.eps * B.eps};
+        const bool fast = B.outer_newton != 0;
+        const int P = kLightThreads / g;
+        const bool active = lane < g * P;
+        const int a = active ? lane % g : 0;
+        const int b = active ? lane / g : 0;
+        const float4 oi = off[s0 + a];
+        float4 vi = make_float4(0.f, 0.f, 0.f, 0.f);
+        if constexpr (MODE == 1) vi = cot_sorted[B.base + s0 + a];
 
         // ---- pieces and run table: wave 0, one lane per row.  Staged layout: the
         //      inner parts of rows 0..24, then their outer parts; the non-empty
@@ -570,6 +592,11 @@ k_light(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
             }
         }
         __syncthreads();
+        int nbox = 0, ncell = 0;
+        if (lane == 0 && nxt < nitems) {
+            nbox = items[nxt].box;
+            ncell = items[nxt].cell0;
+        }
         const int total = uni(sm.total);
         const int inner = uni(sm.inner);
         const bool single = total <= CAP;
@@ -615,15 +642,6 @@ k_light(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
 
         if (single) stage(0, total);
 
-        const Coef k{B.cA, B.cB, B.cC, 2.0f * B.cC, B.eps * B.eps};
-        const bool fast = B.outer_newton != 0;
-        const int P = kLightThreads / g;
-        const bool active = lane < g * P;
-        const int a = active ? lane % g : 0;
-        const int b = active ? lane / g : 0;
-        const float4 oi = off[s0 + a];
-        float4 vi = make_float4(0.f, 0.f, 0.f, 0.f);
-        if constexpr (MODE == 1) vi = cot_sorted[B.base + s0 + a];
         Acc acc;
         for (int u0 = 0; u0 < total; u0 += CAP) {
             const int u1 = min(total, u0 + CAP);
@@ -643,7 +661,8 @@ k_light(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
             }
         }
         // ---- fixed-order pairwise sum over slices: slice b adds slice b + half
-        //      (TwoSum-compensated in the compensated mode)
+        //      (TwoSum-compensated in the compensated mode); red overlays sx
+        __syncthreads();
         if constexpr (COMP) {
             sm.red[0][lane] = acc.x;
             sm.red[1][lane] = acc.y;
@@ -688,7 +707,11 @@ k_light(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
             store(B, s0 + lane, f);
         }
         __syncthreads();
-        if (lane == 0) sm.item = sm.next;
+        if (lane == 0) {
+            sm.item = nxt;
+            sm.ibox = nbox;
+            sm.icell = ncell;
+        }
     }
 }
 
