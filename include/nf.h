@@ -104,10 +104,12 @@ enum {
 typedef struct nf_box {
     int64_t n;
     int32_t K;
-    int32_t dense_min;  /* tile choice: cells with at least this many particles are
-                           summed one sink per lane (sources broadcast), smaller
-                           cells spread over (sink, source-slice) lanes; 0 picks
-                           the library default (33); otherwise 2..65 */
+    int32_t dense_min;  /* tile choice: the sinks of a cell are cut into chunks of
+                           64; a chunk of at least dense_min sinks is summed one
+                           sink per lane (sources broadcast), a smaller one is
+                           spread over (sink, source-slice) lanes.  0 picks the
+                           library default (33); otherwise 2..65.  The workspace
+                           size depends on it (it grows as dense_min falls). */
     double L;
     double eps_s;
     const double *pos;
@@ -128,7 +130,9 @@ const char *nf_last_error(void);
 
 /*
  * Bytes of workspace that nf_bin_particles, nf_accel and nf_accel_vjp need
- * for this set of boxes and flags.  The same workspace serves all three
+ * for this set of boxes (sizes and dense_min) and flags.  The workspace is
+ * scratch only: nothing in it outlives a call, so it may be replaced between
+ * calls, e.g. by a larger one after dense_min is lowered.  The same workspace serves all three
  * (calls on one stream run in order; overlapping calls need separate
  * workspaces).  Returns 0 and sets nf_last_error() if the boxes are invalid.
  */

@@ -126,6 +126,9 @@ int validate(int nbox, const nf_box *boxes, Layout &L) {
         L.N += B.n;
         L.C += ncell;
         L.max_n = std::max<int64_t>(L.max_n, B.n);
+        // a cell of n sinks gives at most n / min(dense_min, 64) dense chunks
+        const int dm = B.dense_min ? B.dense_min : kDefaultDenseMin;
+        L.max_dense += B.n / std::min(dm, 64) + 1;
         L.max_ncell = std::max<int64_t>(L.max_ncell, ncell);
     }
     if (L.N > INT32_MAX) return fail(NF_EUNSUPPORTED, "total particles over all boxes exceed 2^31 - 1");
@@ -165,8 +168,8 @@ int validate(int nbox, const nf_box *boxes, Layout &L) {
     o = align_up(o + 4 * 2 * (size_t)plan_buckets(), 256);
     L.totals_off = o;
     o = align_up(o + 16, 256);
-    // dense items: ceil(n/64) <= 2n/33 per cell of >= 33 particles; light: <= 1 per cell
-    L.max_dense = L.N / 16 + 16;
+    // dense items: at most max_dense (counted per box above); light: <= 1 per cell
+    L.max_dense += 16;
     L.dense_off = o;
     o = align_up(o + sizeof(Item) * (size_t)L.max_dense, 256);
     L.light_off = o;
@@ -202,7 +205,7 @@ void fill_geometry(const nf_box &B, const Layout &L, int b, DevBox &d) {
     d.cB = (float)(-15.0 / (eps * eps * eps * eps));
     d.cC = (float)(6.0 / (eps * eps * eps * eps * eps));
     d.outer_newton = eps <= 1.0 ? 1 : 0;
-    d.dense_min = B.dense_min ? B.dense_min : 33;
+    d.dense_min = B.dense_min ? B.dense_min : kDefaultDenseMin;
     d.pos = B.pos;
     d.off = reinterpret_cast<float4 *>(B.off);
     d.cell_start = B.cell_start;

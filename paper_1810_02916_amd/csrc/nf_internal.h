@@ -8,6 +8,7 @@
 namespace nf {
 
 // Radix sort geometry: 8-bit digits, 256 threads per block, 16 keys per thread.
+constexpr int kDefaultDenseMin = 33;   // nf_box.dense_min == 0
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kSortThreads = 256;

@@ -64,15 +64,25 @@ __device__ int block_sources(const int32_t *cs, int K, int cx, int cy, int cz) {
 // costs in proportion to its block's source count S, a light item to g * S.
 constexpr int kBuckets = 128;
 constexpr int kKinds = 2;                  // 0: dense, 1: light
-constexpr uint32_t kEmptyCell = 0xffffffffu;
 __device__ __forceinline__ int cost_bucket(float pairs) {
     const float l = __log2f(fmaxf(pairs, 1.0f));
     return min(kBuckets - 1, (int)(4.0f * l));
 }
 
-// Per cell: the kind and cost bucket of its items (cellinfo = kind << 16 | bucket,
-// kEmptyCell for an empty cell), and the item counts per (kind, bucket), summed
-// in LDS first so that each block adds one value per non-empty bucket.
+// Items of a cell of n particles: n / 64 full dense chunks, and the last
+// n % 64 sinks as one more dense chunk if they are at least dense_min, else as
+// one light item.  cellinfo packs (dense bucket + 1) | (light bucket + 1) << 16,
+// 0 for none; the item counts per (kind, bucket) are summed in LDS first so
+// that each block adds one value per non-empty bucket.
+struct CellItems {
+    int ndense;     // dense chunks
+    bool light;     // one light item for the remainder
+};
+__device__ __forceinline__ CellItems cell_items(int n, int dense_min) {
+    const int full = n / kUnit, rem = n % kUnit;
+    return CellItems{full + (rem >= dense_min ? 1 : 0), rem > 0 && rem < dense_min};
+}
+
 __global__ void __launch_bounds__(256)
 k_plan_count(const DevBox *boxes, uint32_t *cellinfo, uint32_t *bucket_cnt) {
     __shared__ uint32_t h[kKinds * kBuckets];
@@ -82,18 +92,20 @@ k_plan_count(const DevBox *boxes, uint32_t *cellinfo, uint32_t *bucket_cnt) {
     const int c = blockIdx.x * 256 + threadIdx.x;
     if (c < B.ncell) {
         const int n = B.cell_start[c + 1] - B.cell_start[c];
-        uint32_t info = kEmptyCell;
+        uint32_t info = 0;
         if (n > 0) {
             const int K = B.K;
             const float S = (float)block_sources(B.cell_start, K, c / (K * K), (c / K) % K, c % K);
-            if (n >= B.dense_min) {
+            const CellItems it = cell_items(n, B.dense_min);
+            if (it.ndense) {
                 const int b = cost_bucket(S);
-                atomicAdd(&h[b], (uint32_t)((n + kUnit - 1) / kUnit));
-                info = (uint32_t)b;
-            } else {
-                const int b = cost_bucket((float)n * S);
+                atomicAdd(&h[b], (uint32_t)it.ndense);
+                info |= (uint32_t)(b + 1);
+            }
+            if (it.light) {
+                const int b = cost_bucket((float)(n % kUnit) * S);
                 atomicAdd(&h[kBuckets + b], 1u);
-                info = (1u << 16) | (uint32_t)b;
+                info |= (uint32_t)(b + 1) << 16;
             }
         }
         cellinfo[B.cellbase + c] = info;
@@ -131,28 +143,29 @@ k_plan_emit(const DevBox *boxes, const uint32_t *__restrict__ cellinfo,
     __syncthreads();
     const DevBox &B = boxes[blockIdx.y];
     const int c = blockIdx.x * 256 + threadIdx.x;
-    uint32_t info = kEmptyCell, slot = 0, rank = 0;
-    int n = 0;
+    uint32_t info = 0, rd = 0, rl = 0;
+    int n = 0, bd = 0, bl = 0;
+    CellItems it{0, false};
     if (c < B.ncell) {
         info = cellinfo[B.cellbase + c];
-        if (info != kEmptyCell) {
+        if (info) {
             n = B.cell_start[c + 1] - B.cell_start[c];
-            slot = (info >> 16) * kBuckets + (info & 0xffffu);
-            rank = atomicAdd(&h[slot], info >> 16 ? 1u : (uint32_t)((n + kUnit - 1) / kUnit));
+            it = cell_items(n, B.dense_min);
+            bd = (int)(info & 0xffffu) - 1;
+            bl = (int)(info >> 16) - 1;
+            if (it.ndense) rd = atomicAdd(&h[bd], (uint32_t)it.ndense);
+            if (it.light) rl = atomicAdd(&h[kBuckets + bl], 1u);
         }
     }
     __syncthreads();
     for (int t = threadIdx.x; t < kKinds * kBuckets; t += 256)
         if (h[t]) base[t] = bucket_off[t] + atomicAdd(&bucket_cur[t], h[t]);
     __syncthreads();
-    if (info == kEmptyCell) return;
-    const uint32_t at = base[slot] + rank;
-    if (info >> 16) {
-        light[at] = Item{(int)blockIdx.y, c, 1, 0};
-    } else {
-        const int nch = (n + kUnit - 1) / kUnit;
-        for (int k = 0; k < nch; ++k) dense[at + k] = Item{(int)blockIdx.y, c, 1, k};
+    if (it.ndense) {
+        const uint32_t at = base[bd] + rd;
+        for (int k = 0; k < it.ndense; ++k) dense[at + k] = Item{(int)blockIdx.y, c, 1, k};
     }
+    if (it.light) light[base[kBuckets + bl] + rl] = Item{(int)blockIdx.y, c, 1, n / kUnit};
 }
 
 // ------------------------------------------------------------------ pair arithmetic
@@ -389,7 +402,7 @@ struct LightSmem {
     float4 rd[kPiece];               // per run: (global minus staged index, dx, dy, z bias)
     int nrun;
     int item;                        // current item and its (box, cell)
-    int ibox, icell;
+    int ibox, icell, ichunk;
     int inner;                       // staged particles of the 27 inner cells
     int total;
 };
@@ -468,13 +481,14 @@ k_light(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
         if (first < nitems) {
             sm.ibox = items[first].box;
             sm.icell = items[first].cell0;
+            sm.ichunk = items[first].chunk;
         }
     }
     for (;;) {
         __syncthreads();
         const int itx = uni(sm.item);
         if (itx >= nitems) break;
-        const int ibox = uni(sm.ibox), cell0 = uni(sm.icell);
+        const int ibox = uni(sm.ibox), cell0 = uni(sm.icell), chunk = uni(sm.ichunk);
         // claim the next item now (lane 0); its record is fetched once the setup
         // below is done, and both complete while this item runs
         int nxt = 0;
@@ -484,8 +498,8 @@ k_light(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
         const int cx = cell0 / (K * K), cy = (cell0 / K) % K, z = cell0 % K;
         const int32_t *__restrict__ cs = B.cell_start;
         const float4 *__restrict__ off = B.off;
-        const int s0 = uni(cs[cell0]);
-        const int g = uni(cs[cell0 + 1]) - s0;
+        const int s0 = uni(cs[cell0]) + kUnit * chunk;
+        const int g = min(uni(cs[cell0 + 1]) - s0, kUnit);
 
         // ---- this lane's sink (sink a, source slice b), loaded before the setup
         const Coef k{B.cA, B.cB, B.cC, 2.0f * B.cC, B.eps * B.eps};
@@ -592,10 +606,11 @@ k_light(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
             }
         }
         __syncthreads();
-        int nbox = 0, ncell = 0;
+        int nbox = 0, ncell = 0, nchunk = 0;
         if (lane == 0 && nxt < nitems) {
             nbox = items[nxt].box;
             ncell = items[nxt].cell0;
+            nchunk = items[nxt].chunk;
         }
         const int total = uni(sm.total);
         const int inner = uni(sm.inner);
@@ -711,6 +726,7 @@ k_light(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
             sm.item = nxt;
             sm.ibox = nbox;
             sm.icell = ncell;
+            sm.ichunk = nchunk;
         }
     }
 }

@@ -91,6 +91,18 @@ class Binned:
     def nbad(self) -> List[int]:
         return [int(b.nbad.item()) for b in self.boxes]
 
+    def set_dense_min(self, v: int) -> None:
+        """Change the force kernels' tile choice (0: library default) for all
+        boxes; the workspace grows if the new choice needs more."""
+        for bx in self.boxes:
+            bx.dense_min = int(v)
+        self._arr = None
+        need = _lib.load().nf_workspace_bytes(self.nbox, self.carray(), 0)
+        if need == 0:
+            _lib.check(_lib.NF_EINVAL)
+        if need > self.workspace.numel():
+            self.workspace = torch.empty(int(need), dtype=torch.uint8, device=self.device)
+
 
 def _prep_pos(pos: torch.Tensor) -> torch.Tensor:
     if not isinstance(pos, torch.Tensor) or not pos.is_cuda:

@@ -1,8 +1,9 @@
 """Autotuner for the force kernels' tile choice.
 
-The one tunable is ``dense_min``: cells with at least that many particles are
-summed one sink per lane with broadcast sources, smaller cells are spread
-over (sink, source-slice) lanes with LDS-staged sources.  The best split
+The one tunable is ``dense_min``: the sinks of a cell are cut into chunks of
+64, and a chunk of at least ``dense_min`` sinks is summed one sink per lane
+with broadcast sources, a smaller one is spread over (sink, source-slice)
+lanes with LDS-staged sources.  The best split
 depends on the occupancy distribution of the workload, so the tuner times
 the compensated acceleration pass for a few candidates on the caller's own
 binned boxes and keeps the fastest.  Results are cached per workload
@@ -19,7 +20,7 @@ import torch
 
 from . import nearfield as nfp
 
-CANDIDATES = (17, 25, 33, 41, 49, 65)
+CANDIDATES = (9, 17, 25, 33, 41, 49, 57, 65)
 
 
 def _table_path() -> str:
@@ -39,9 +40,7 @@ def signature(b: nfp.Binned) -> str:
 
 
 def _set_dense_min(b: nfp.Binned, v: int) -> None:
-    for bx in b.boxes:
-        bx.dense_min = int(v)
-    b._arr = None   # rebuild the descriptor array
+    b.set_dense_min(v)
 
 
 def _time(fn, reps: int) -> float:

@@ -257,6 +257,29 @@ def test_tile_paths_small_K_dense_and_sparse(K):
     assert err_stats(g, refg)["rms"] <= TOL_PLAIN
 
 
+@pytest.mark.parametrize("dense_min", [2, 17, 65])
+def test_tile_choice_dense_min(dense_min):
+    """Every split between the two tile kernels gives the oracle's result:
+    dense_min 2 (almost every chunk dense), 17, and 65 (only full 64-sink
+    chunks dense, every remainder light).  The binning is reused and the
+    workspace regrown by set_dense_min."""
+    sp = WORKLOADS["clustered262k"]
+    pos = make_box(sp)
+    b = nfp.bin_particles(_gpu(pos), sp.K, sp.L, sp.eps_s)
+    b.set_dense_min(dense_min)
+    print(f"[dense_min] {dense_min}", flush=True)
+    ref = oracle.accel(pos, sp.K, sp.L, sp.eps_s)
+    for comp in (False, True):
+        got = nfp.accel(b, 1.0, compensated=comp).cpu().numpy().astype(np.float64)
+        st = err_stats(got, ref)
+        print(dense_min, comp, st)
+        assert st["rms"] <= (TOL_COMP if comp else TOL_PLAIN), st
+    v = gaussian_cotangent(sp.n, 5 + dense_min).astype(np.float32)
+    g = nfp.accel_vjp(b, torch.from_numpy(v).to(DEV), 1.0, compensated=True).cpu().numpy()
+    refg = oracle.jvp(pos, sp.K, sp.L, sp.eps_s, v.astype(np.float64))
+    assert err_stats(g, refg)["rms"] <= TOL_PLAIN
+
+
 def test_tile_large_softening_uses_spline_everywhere():
     """eps above one cell width: the outer-shell Newton shortcut must be off."""
     K, L = 8, 1.0
