@@ -23,6 +23,8 @@
 // closest pairs are formed from the exact float offsets, and a cell of the
 // outer shell of the block (some |d| = 2) is at r >= 1 and takes the Newton
 // branch directly when eps <= 1.
+#include <climits>
+
 #include "nf_internal.h"
 #include "nf_kernels.h"
 
@@ -276,6 +278,13 @@ __device__ __forceinline__ void store(const DevBox &B, int slot, float3 f) {
 // ------------------------------------------------------------------ dense path
 
 typedef const __attribute__((address_space(4))) float cfloat;
+typedef const __attribute__((address_space(1))) float gfloat;
+
+// A float4 of a global array through a global-address-space pointer (plain
+// pointers loaded from a descriptor compile to flat loads).
+__device__ __forceinline__ float4 ld_global4(gfloat *p, int i) {
+    return make_float4(p[4 * i], p[4 * i + 1], p[4 * i + 2], p[4 * i + 3]);
+}
 
 // Sources [j0, j1) of one cell through scalar loads.
 template <int MODE, bool SPLINE, bool COMP>
@@ -398,9 +407,9 @@ struct LightSmem {
         float red[6][kLightThreads];     // after the sum: slice partials (sum, compensation)
     };
     float2 sv[MODE == 1 ? CAP : 1];  // (v_y, v_z) for the VJP
-    int rs[128];                     // staged start of each non-empty piece (run), ascending
+    int rs[128];                     // staged start of each non-empty piece (run), ascending,
+                                     // then INT_MAX
     float4 rd[kPiece];               // per run: (global minus staged index, dx, dy, z bias)
-    int nrun;
     int item;                        // current item and its (box, cell)
     int ibox, icell, ichunk;
     int inner;                       // staged particles of the 27 inner cells
@@ -461,7 +470,7 @@ __device__ __forceinline__ void segment(const float4 *__restrict__ sx, const flo
 }
 
 template <int MODE, bool COMP, int CAP>
-__global__ void __launch_bounds__(kLightThreads) __attribute__((amdgpu_waves_per_eu(6)))
+__global__ void __launch_bounds__(kLightThreads) __attribute__((amdgpu_waves_per_eu(MODE == 0 ? 8 : 6)))
 k_light(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
         const uint32_t *__restrict__ totals, uint32_t *counter,
         const float4 *__restrict__ cot_sorted) {
@@ -498,6 +507,8 @@ k_light(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
         const int cx = cell0 / (K * K), cy = (cell0 / K) % K, z = cell0 % K;
         const int32_t *__restrict__ cs = B.cell_start;
         const float4 *__restrict__ off = B.off;
+        gfloat *goff = (gfloat *)B.off;
+        gfloat *gcot = (gfloat *)cot_sorted;
         const int s0 = uni(cs[cell0]) + kUnit * chunk;
         const int g = min(uni(cs[cell0 + 1]) - s0, kUnit);
 
@@ -599,10 +610,12 @@ k_light(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
                     }
                 }
             }
+            // pad the run starts: the search reads any index below 128
+            if (r >= kin + kout) sm.rs[r] = INT_MAX;
+            if (r + 64 >= kin + kout) sm.rs[r + 64] = INT_MAX;
             if (r == 0) {
                 sm.inner = tin;
                 sm.total = tin + tout;
-                sm.nrun = kin + kout;
             }
         }
         __syncthreads();
@@ -617,39 +630,50 @@ k_light(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
         const bool single = total <= CAP;
 
         // stage the union window [u0, u1): thread t takes elements u0 + t + 256 i,
-        // finds its run by a fixed 7-step binary search over the run starts,
+        // finds their runs by a branch-free 7-step binary search over the run
+        // starts (padded with INT_MAX), the searches of its elements interleaved,
         // and issues all its loads before any LDS store
         auto stage = [&](int u0, int u1) {
             constexpr int kPer = CAP / kLightThreads;
-            const int nrun = uni(sm.nrun);
-            float4 buf[kPer], cb[kPer], dsc[kPer];
-            int dl[kPer];
+            int pos[kPer], d[kPer];
 #pragma unroll
             for (int i = 0; i < kPer; ++i) {
-                const int d = u0 + lane + kLightThreads * i;
-                dl[i] = d < u1 ? d - u0 : -1;
-                if (d < u1) {
-                    int pos = 0;
+                pos[i] = 0;
+                d[i] = u0 + lane + kLightThreads * i;
+            }
 #pragma unroll
-                    for (int st = 64; st > 0; st >>= 1)
-                        if (pos + st < nrun && sm.rs[pos + st] <= d) pos += st;
-                    dsc[i] = sm.rd[pos];
-                    const int gsrc = d + __float_as_int(dsc[i].x);
-                    buf[i] = off[gsrc];
-                    if constexpr (MODE == 1) cb[i] = cot_sorted[B.base + gsrc];
+            for (int st = 64; st > 0; st >>= 1) {
+#pragma unroll
+                for (int i = 0; i < kPer; ++i) {
+                    const int c = pos[i] + st;
+                    pos[i] = sm.rs[c] <= d[i] ? c : pos[i];
+                }
+            }
+            float4 buf[kPer], cb[kPer];
+            float sh[kPer][3];
+#pragma unroll
+            for (int i = 0; i < kPer; ++i) {
+                if (d[i] < u1) {
+                    const float4 dsc = sm.rd[pos[i]];
+                    const int gsrc = d[i] + __float_as_int(dsc.x);
+                    buf[i] = ld_global4(goff, gsrc);
+                    if constexpr (MODE == 1) cb[i] = ld_global4(gcot, B.base + gsrc);
+                    sh[i][0] = dsc.y;
+                    sh[i][1] = dsc.z;
+                    sh[i][2] = dsc.w;
                 }
             }
 #pragma unroll
             for (int i = 0; i < kPer; ++i) {
-                if (dl[i] >= 0) {
+                if (d[i] < u1) {
                     const float4 o = buf[i];
-                    float4 v = make_float4(o.x + dsc[i].y, o.y + dsc[i].z, o.z + (o.w + dsc[i].w),
+                    float4 v = make_float4(o.x + sh[i][0], o.y + sh[i][1], o.z + (o.w + sh[i][2]),
                                            0.f);
                     if constexpr (MODE == 1) {
                         v.w = cb[i].x;
-                        sm.sv[dl[i]] = make_float2(cb[i].y, cb[i].z);
+                        sm.sv[d[i] - u0] = make_float2(cb[i].y, cb[i].z);
                     }
-                    sm.sx[dl[i]] = v;
+                    sm.sx[d[i] - u0] = v;
                 }
             }
             __syncthreads();
