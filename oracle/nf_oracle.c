@@ -177,6 +177,36 @@ static void spline_jacobian(const double r[3], double eps, double J[9]) {
             J[3 * a + b] = (a == b ? g : 0.0) + h * r[a] * r[b];
 }
 
+/* Plummer-softened pair force in cell units (Sec. 4.3, the Plummer law):
+   F = r / (rho^2 + eps^2)^(3/2).  Finite at r = 0, where F = 0. */
+static void plummer_force(const double r[3], double eps, double F[3]) {
+    double w = r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + eps * eps;
+    double g = 1.0 / (w * sqrt(w));
+    F[0] = g * r[0];
+    F[1] = g * r[1];
+    F[2] = g * r[2];
+}
+
+/* Jacobian of the Plummer force: g = w^(-3/2), h = g'(rho)/rho = -3 w^(-5/2),
+   with w = rho^2 + eps^2. */
+static void plummer_jacobian(const double r[3], double eps, double J[9]) {
+    double w = r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + eps * eps;
+    double g = 1.0 / (w * sqrt(w));
+    double h = -3.0 * g / w;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            J[3 * a + b] = (a == b ? g : 0.0) + h * r[a] * r[b];
+}
+
+/* Softening law: 0 = Eq. 2 spline (eps = spline radius), 1 = Plummer (eps = eps_p). */
+static void pair_force(int law, const double r[3], double eps, double F[3]) {
+    if (law == 1) plummer_force(r, eps, F); else spline_force(r, eps, F);
+}
+
+static void pair_jacobian(int law, const double r[3], double eps, double J[9]) {
+    if (law == 1) plummer_jacobian(r, eps, J); else spline_jacobian(r, eps, J);
+}
+
 /* Internal binned view built by the force routines below. */
 typedef struct {
     int64_t n;
@@ -270,9 +300,10 @@ static int binned_build(binned_t *b, int64_t n, const double *pos, int32_t K,
  * *interactions when non-NULL.
  */
 int oracle_accel(int64_t n, const double *pos, int32_t K, double L, double eps_s,
-                 double gm, int round_offsets, int64_t nsink, const int64_t *sinks,
+                 double gm, int law, int round_offsets, int64_t nsink, const int64_t *sinks,
                  double *acc, int64_t *interactions) {
-    if (!(eps_s > 0) || !isfinite(eps_s) || !isfinite(gm)) return OR_EINVAL;
+    if (!(eps_s > 0) || !isfinite(eps_s) || !isfinite(gm) || law < 0 || law > 1)
+        return OR_EINVAL;
     binned_t b;
     int rc = binned_build(&b, n, pos, K, L, round_offsets);
     if (rc != OR_OK) return rc;
@@ -292,7 +323,7 @@ int oracle_accel(int64_t n, const double *pos, int32_t K, double L, double eps_s
         int64_t cnt = 0;
         FOR_EACH_NEIGHBOUR(&b, i, r, j, {
             double F[3];
-            spline_force(r, eps, F);
+            pair_force(law, r, eps, F);
             ax += F[0];
             ay += F[1];
             az += F[2];
@@ -316,9 +347,10 @@ int oracle_accel(int64_t n, const double *pos, int32_t K, double L, double eps_s
  * tvec and out are [n][3] in input order (out: [nsink][3] if sinks given).
  */
 int oracle_jvp(int64_t n, const double *pos, int32_t K, double L, double eps_s,
-               double gm, const double *tvec, int64_t nsink, const int64_t *sinks,
+               double gm, int law, const double *tvec, int64_t nsink, const int64_t *sinks,
                double *out) {
-    if (!(eps_s > 0) || !isfinite(eps_s) || !isfinite(gm)) return OR_EINVAL;
+    if (!(eps_s > 0) || !isfinite(eps_s) || !isfinite(gm) || law < 0 || law > 1)
+        return OR_EINVAL;
     binned_t b;
     int rc = binned_build(&b, n, pos, K, L, 0);
     if (rc != OR_OK) return rc;
@@ -336,7 +368,7 @@ int oracle_jvp(int64_t n, const double *pos, int32_t K, double L, double eps_s,
         double o0 = 0.0, o1 = 0.0, o2 = 0.0;
         FOR_EACH_NEIGHBOUR(&b, i, r, j, {
             double J[9];
-            spline_jacobian(r, eps, J);
+            pair_jacobian(law, r, eps, J);
             double d0 = tvec[3 * j] - tvec[3 * i];
             double d1 = tvec[3 * j + 1] - tvec[3 * i + 1];
             double d2 = tvec[3 * j + 2] - tvec[3 * i + 2];
@@ -360,8 +392,9 @@ int oracle_jvp(int64_t n, const double *pos, int32_t K, double L, double eps_s,
  * Serial (it scatters into shared outputs).  v and out are [n][3], input order.
  */
 int oracle_vjp(int64_t n, const double *pos, int32_t K, double L, double eps_s,
-               double gm, const double *v, double *out) {
-    if (!(eps_s > 0) || !isfinite(eps_s) || !isfinite(gm)) return OR_EINVAL;
+               double gm, int law, const double *v, double *out) {
+    if (!(eps_s > 0) || !isfinite(eps_s) || !isfinite(gm) || law < 0 || law > 1)
+        return OR_EINVAL;
     binned_t b;
     int rc = binned_build(&b, n, pos, K, L, 0);
     if (rc != OR_OK) return rc;
@@ -371,7 +404,7 @@ int oracle_vjp(int64_t n, const double *pos, int32_t K, double L, double eps_s,
     for (int64_t i = 0; i < n; ++i) {
         FOR_EACH_NEIGHBOUR(&b, i, r, j, {
             double J[9];
-            spline_jacobian(r, eps, J);
+            pair_jacobian(law, r, eps, J);
             /* block (i, j): +J ; block (i, i): -J.  Transpose applied to v_i. */
             for (int a = 0; a < 3; ++a) {
                 double col = J[0 + a] * v[3 * i] + J[3 + a] * v[3 * i + 1] + J[6 + a] * v[3 * i + 2];

@@ -1,8 +1,8 @@
 """ctypes front end of the C oracle (``nf_oracle.c``).
 
 TEST INFRASTRUCTURE ONLY: the oracle defines what the near-field force is
-(Sec. 2.1 cell decomposition with R = 2, Sec. 4.3 Eq. 2 spline softening,
-Sec. 4.5 FP64 comparison) and is never called by the product path.
+(Sec. 2.1 cell decomposition with R = 2, Sec. 4.3 Eq. 2 spline softening or
+the Plummer law of the same section, Sec. 4.5 FP64 comparison) and is never called by the product path.
 """
 from __future__ import annotations
 
@@ -48,9 +48,10 @@ def _get():
         i64, i32, dbl, vp = ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_void_p
         lib.oracle_cells.argtypes = [i64, vp, i32, dbl, vp, vp]
         lib.oracle_bin.argtypes = [i64, vp, i32, dbl, vp, vp, vp]
-        lib.oracle_accel.argtypes = [i64, vp, i32, dbl, dbl, dbl, ctypes.c_int, i64, vp, vp, vp]
-        lib.oracle_jvp.argtypes = [i64, vp, i32, dbl, dbl, dbl, vp, i64, vp, vp]
-        lib.oracle_vjp.argtypes = [i64, vp, i32, dbl, dbl, dbl, vp, vp]
+        ci = ctypes.c_int
+        lib.oracle_accel.argtypes = [i64, vp, i32, dbl, dbl, dbl, ci, ci, i64, vp, vp, vp]
+        lib.oracle_jvp.argtypes = [i64, vp, i32, dbl, dbl, dbl, ci, vp, i64, vp, vp]
+        lib.oracle_vjp.argtypes = [i64, vp, i32, dbl, dbl, dbl, ci, vp, vp]
         lib.oracle_interactions.argtypes = [i64, vp, i32, dbl, vp]
         lib.oracle_num_threads.restype = ctypes.c_int
         lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
@@ -107,40 +108,53 @@ def bin_particles(pos, K: int, L: float):
     return cs, order, off
 
 
+LAWS = {"spline": 0, "plummer": 1}
+
+
+def _law(law: str) -> int:
+    if law not in LAWS:
+        raise ValueError(f"law must be one of {sorted(LAWS)}")
+    return LAWS[law]
+
+
 def accel(pos, K: int, L: float, eps_s: float, gm: float = 1.0, *,
-          round_offsets: bool = False, sinks=None, return_count: bool = False):
-    """FP64 accelerations [n,3] (or [len(sinks),3]) in input order."""
+          round_offsets: bool = False, sinks=None, return_count: bool = False,
+          law: str = "spline"):
+    """FP64 accelerations [n,3] (or [len(sinks),3]) in input order.  ``law``:
+    "spline" (Eq. 2, eps_s is the spline radius) or "plummer" (eps_s is the
+    Plummer length)."""
     p = _pos(pos)
     n = p.shape[0]
     s = None if sinks is None else np.ascontiguousarray(np.asarray(sinks, dtype=np.int64))
     m = n if s is None else s.shape[0]
     out = np.empty((m, 3), dtype=np.float64)
     cnt = np.zeros(1, dtype=np.int64)
-    _check(_get().oracle_accel(n, _p(p), int(K), float(L), float(eps_s), float(gm),
+    _check(_get().oracle_accel(n, _p(p), int(K), float(L), float(eps_s), float(gm), _law(law),
                                1 if round_offsets else 0, m, _p(s), _p(out), _p(cnt)),
            "oracle_accel")
     return (out, int(cnt[0])) if return_count else out
 
 
-def jvp(pos, K: int, L: float, eps_s: float, tvec, gm: float = 1.0, *, sinks=None):
+def jvp(pos, K: int, L: float, eps_s: float, tvec, gm: float = 1.0, *, sinks=None,
+        law: str = "spline"):
     p = _pos(pos)
     n = p.shape[0]
     t = _pos(tvec)
     s = None if sinks is None else np.ascontiguousarray(np.asarray(sinks, dtype=np.int64))
     m = n if s is None else s.shape[0]
     out = np.empty((m, 3), dtype=np.float64)
-    _check(_get().oracle_jvp(n, _p(p), int(K), float(L), float(eps_s), float(gm), _p(t),
-                             m, _p(s), _p(out)), "oracle_jvp")
+    _check(_get().oracle_jvp(n, _p(p), int(K), float(L), float(eps_s), float(gm), _law(law),
+                             _p(t), m, _p(s), _p(out)), "oracle_jvp")
     return out
 
 
-def vjp(pos, K: int, L: float, eps_s: float, v, gm: float = 1.0):
+def vjp(pos, K: int, L: float, eps_s: float, v, gm: float = 1.0, *, law: str = "spline"):
     p = _pos(pos)
     n = p.shape[0]
     vv = _pos(v)
     out = np.empty((n, 3), dtype=np.float64)
-    _check(_get().oracle_vjp(n, _p(p), int(K), float(L), float(eps_s), float(gm), _p(vv),
-                             _p(out)), "oracle_vjp")
+    _check(_get().oracle_vjp(n, _p(p), int(K), float(L), float(eps_s), float(gm), _law(law),
+                             _p(vv), _p(out)), "oracle_vjp")
     return out
 
 

@@ -14,7 +14,10 @@ wrong sign, a wrong neighbour set, a transposed Jacobian):
     them;
   * invariances (permutation, whole-cell translation, scaling, gm);
   * derivative pins: central finite differences, J = J^T, sum rules and the
-    closed-form two-body Jacobian.
+    closed-form two-body Jacobian;
+  * the Plummer law of Sec. 4.3: two-body closed form, open and minimum-image
+    direct sums, its Jacobian, and the equal-minimum-dynamical-time relation
+    behind the printed eps_s = 2.16 eps_p.
 """
 import os
 
@@ -352,3 +355,108 @@ def test_two_body_jacobian_closed_form():
     v = np.array([[0.0, 0.0, 0.0], [1.0, 2.0, 3.0]])
     xbar = oracle.vjp(p, K, L, eps, v)
     np.testing.assert_allclose(xbar[0], _golden()["c0"] / eps ** 3 * v[1], rtol=1e-12)
+
+
+# ------------------------------------------------------------------ Plummer law (Sec. 4.3)
+
+def _plummer_two_body(r, eps, K=16, L=1.0, gm=1.0, x0=0.37):
+    p = np.full((2, 3), 0.41)
+    p[0, 0] = x0
+    p[1, 0] = x0 + r
+    return oracle.accel(p, K, L, eps, gm, law="plummer")
+
+
+@pytest.mark.parametrize("r", [0.001, 0.004, 0.01, 0.03, 0.09])
+def test_plummer_two_body_closed_form(r):
+    """a = gm d / (|d|^2 + eps_p^2)^(3/2), inside and outside eps_p."""
+    eps, gm = 0.01, 1.7
+    acc = _plummer_two_body(r, eps, gm=gm)
+    F = gm * r / (r * r + eps * eps) ** 1.5
+    np.testing.assert_allclose(acc[0], [F, 0, 0], rtol=1e-12, atol=1e-12 * F)
+    np.testing.assert_allclose(acc[1], [-F, 0, 0], rtol=1e-12, atol=1e-12 * F)
+
+
+def test_plummer_coincident_pair_and_far_limit():
+    p = np.array([[0.3, 0.3, 0.3], [0.3, 0.3, 0.3]])
+    np.testing.assert_array_equal(oracle.accel(p, 8, 1.0, 0.05, law="plummer"), 0.0)
+    # far from eps_p the law tends to Newton with relative deviation ~ 1.5 (eps/r)^2
+    r, eps = 0.1, 1e-4
+    a = _plummer_two_body(r, eps)[0, 0]
+    assert abs(a * r * r - 1.0) < 2 * 1.5 * (eps / r) ** 2
+
+
+def test_plummer_compact_cluster_equals_open_direct_sum():
+    K, L = 20, 4.0
+    h = L / K
+    rng = np.random.default_rng(19)
+    pos = 7 * h + h * rng.uniform(0.05, 0.95, size=(300, 3))
+    eps = 0.01
+    d = pos[None, :, :] - pos[:, None, :]
+    w = (d ** 2).sum(2) + eps * eps
+    ref = (d / w[:, :, None] ** 1.5).sum(1)
+    np.testing.assert_allclose(oracle.accel(pos, K, L, eps, law="plummer"), ref, rtol=1e-10,
+                               atol=1e-12 * np.abs(ref).max())
+
+
+def test_plummer_K5_equals_minimum_image_sum():
+    K, L = 5, 1.0
+    h = L / K
+    rng = np.random.default_rng(15)
+    c = rng.integers(0, K, size=(500, 3))
+    pos = (c + 0.5 + rng.uniform(-0.25, 0.25, size=(500, 3))) * h
+    eps = 0.05 * h
+    ref = np.zeros_like(pos)
+    for i in range(len(pos)):
+        d = pos - pos[i]
+        d -= L * np.round(d / L)
+        w = (d ** 2).sum(1) + eps * eps
+        ref[i] = (d / w[:, None] ** 1.5).sum(0)
+    np.testing.assert_allclose(oracle.accel(pos, K, L, eps, law="plummer"), ref, rtol=1e-11,
+                               atol=1e-11 * np.abs(ref).max())
+
+
+def test_plummer_jacobian_pins():
+    """Central differences, J = J^T (scatter VJP = gather JVP) and the closed
+    two-body Jacobian (I w - 3 d d^T) / w^(5/2), w = |d|^2 + eps_p^2."""
+    K, L = 8, 1.0
+    pos = clustered_box(2000, 12, K, L, 1.5, 0.5, seed=22)
+    eps = 0.004
+    h = 1e-6 * (L / 12)
+    t = _frozen_tangent(pos, K, L, h, 51)
+    fd = (oracle.accel(pos + h * t, K, L, eps, law="plummer")
+          - oracle.accel(pos - h * t, K, L, eps, law="plummer")) / (2 * h)
+    jt = oracle.jvp(pos, K, L, eps, t, law="plummer")
+    assert np.sqrt(((fd - jt) ** 2).sum() / (jt ** 2).sum()) < 1e-6
+    v = gaussian_cotangent(len(pos), 52)
+    a = oracle.vjp(pos, K, L, eps, v, 1.3, law="plummer")
+    b = oracle.jvp(pos, K, L, eps, v, 1.3, law="plummer")
+    assert np.abs(a - b).max() <= 1e-10 * np.abs(b).max()
+    rng = np.random.default_rng(4)
+    for r in (0.003, 0.05):
+        dvec = rng.normal(size=3)
+        dvec *= r / np.linalg.norm(dvec)
+        p = np.array([[0.5, 0.5, 0.5], 0.5 + dvec])
+        v = np.array([[0.0, 0.0, 0.0], [1.0, -2.0, 0.5]])
+        xbar = oracle.vjp(p, 16, 1.0, 0.01, v, law="plummer")
+        w = r * r + 1e-4
+        J = (np.eye(3) * w - 3 * np.outer(dvec, dvec)) / w ** 2.5
+        np.testing.assert_allclose(xbar[0], J @ v[1], rtol=1e-10)
+
+
+def test_spline_plummer_equal_minimum_dynamical_time():
+    """Sec. 4.3 converts a Plummer length to the spline radius giving the same
+    minimum pairwise dynamical time, which is set by the largest F/r: 1/eps_p^3
+    for Plummer (at r = 0) and 10/eps_s^3 for Eq. 2 (also at r -> 0).  Equal
+    at eps_s = 10^(1/3) eps_p = 2.154 eps_p; the printed 2.16 is that root to
+    three digits."""
+    eps_p = 0.004
+    r = 1e-9   # F/r at r -> 0: the spline's leading correction is 1.5 r/eps_s ~ 2e-7
+    gp = _plummer_two_body(r, eps_p)[0, 0] / r
+    g_exact = _two_body(r, 10 ** (1 / 3) * eps_p)[0, 0] / r
+    g_paper = _two_body(r, _golden()["spline_per_plummer"] * eps_p)[0, 0] / r
+    assert abs(g_exact / gp - 1) < 1e-6
+    assert abs(g_paper / gp - 1) < 1e-2
+    # the spline's F/r is largest at r -> 0 (it decreases on (0, eps_s))
+    eps_s = 2.16 * eps_p
+    gs = [_two_body(u * eps_s, eps_s)[0, 0] / (u * eps_s) for u in (1e-6, 0.2, 0.5, 0.9, 1.5)]
+    assert all(a > b for a, b in zip(gs, gs[1:]))
