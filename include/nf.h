@@ -75,7 +75,11 @@ enum {
     NF_COMPENSATED = 1u << 0,
     /* Reference kernel: one sink per thread, sources read straight from
        global memory.  Same arithmetic, slower; kept for cross-checks. */
-    NF_SIMPLE = 1u << 1
+    NF_SIMPLE = 1u << 1,
+    /* Plummer softening instead of Eq. 2 (Sec. 4.3, the Plummer law):
+       F(r) = r / (r^2 + eps_p^2)^(3/2) for every pair of the block, with the
+       box's eps_s field read as the Plummer length eps_p. */
+    NF_PLUMMER = 1u << 2
 };
 
 /* Upper bound on boxes per call. */
@@ -153,7 +157,8 @@ int nf_bin_particles(int nbox, const nf_box *boxes, void *ws, size_t ws_bytes,
  *   of gm / L^2), float, [n_b][3] in caller order.
  * Requires the boxes as filled by nf_bin_particles (off, cell_start, order);
  * pos is not read.  acc is an array of nbox device pointers (host array).
- * Arithmetic: FP32 on cell offsets; flags may add NF_COMPENSATED.
+ * Arithmetic: FP32 on cell offsets; flags may add NF_COMPENSATED, and
+ * NF_PLUMMER selects the Plummer law in place of Eq. 2.
  */
 int nf_accel(int nbox, const nf_box *boxes, double gm, uint32_t flags,
              float *const *acc, void *ws, size_t ws_bytes, void *stream);

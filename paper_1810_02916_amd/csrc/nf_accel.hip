@@ -6,7 +6,8 @@
 // sources read from global memory cell by cell.  Arithmetic per pair, in
 // cell widths with the sink shifted into the source cell's frame:
 //   r   = o_j - (o_i - d)                 (3 sub)
-//   r2  = r.r + tiny                      (3 fma; tiny makes r = 0 give 0)
+//   r2  = r.r + floor                     (3 fma; floor = 1e-30 makes r = 0 give
+//                                          0, or eps_p^2 for the Plummer law)
 //   q   = rsq(r2), q3 = q^3               (1 rsq, 2 mul)
 //   f   = min(cA + cB rho + cC rho^2, q3) (rho = r2 q; the paper's single-min
 //                                          form of Eq. 2, Sec. 4.3 footnote)
@@ -18,10 +19,6 @@
 
 namespace nf {
 
-// Smallest float added to r^2: keeps rsq finite for coincident pairs, whose
-// force is then min(poly, inf) * 0 = 0, and is far below half an ulp of any
-// separation that floats can resolve between offsets of order one.
-constexpr float kTiny = 1.0e-30f;
 
 __device__ __forceinline__ int find_cell(const int32_t *__restrict__ cs, int ncell, int s) {
     int lo = 0, hi = ncell;   // cs[lo] <= s < cs[hi]
@@ -66,6 +63,8 @@ __global__ void __launch_bounds__(256) k_accel_simple(const DevBox *boxes) {
     const float4 oi = off[s];
     const float cA = B.cA, cB = B.cB, cC = B.cC;
     const bool fast = B.outer_newton != 0;
+    const bool plummer = B.plummer != 0;
+    const float floor2 = B.r2floor;
     Acc3 a;
     for (int dx = -2; dx <= 2; ++dx) {
         const int nx = wrap(cx + dx, K);
@@ -76,12 +75,14 @@ __global__ void __launch_bounds__(256) k_accel_simple(const DevBox *boxes) {
                 const int nc = row + wrap(cz + dz, K);
                 const int j0 = max(cs[nc], 0), j1 = min(cs[nc + 1], B.n);
                 const float sx = oi.x - (float)dx, sy = oi.y - (float)dy, sz = oi.z - (float)dz;
-                const bool outer = fast && (dx == -2 || dx == 2 || dy == -2 || dy == 2 ||
-                                            dz == -2 || dz == 2);
+                // f = q^3 for the outer shell (eps <= 1) and for every pair of
+                // the Plummer law (whose eps_p^2 is in the r^2 floor)
+                const bool outer = plummer || (fast && (dx == -2 || dx == 2 || dy == -2 ||
+                                                        dy == 2 || dz == -2 || dz == 2));
                 for (int j = j0; j < j1; ++j) {
                     const float4 oj = off[j];
                     const float rx = oj.x - sx, ry = oj.y - sy, rz = oj.z - sz;
-                    float r2 = __builtin_fmaf(rx, rx, kTiny);
+                    float r2 = __builtin_fmaf(rx, rx, floor2);
                     r2 = __builtin_fmaf(ry, ry, r2);
                     r2 = __builtin_fmaf(rz, rz, r2);
                     const float q = __builtin_amdgcn_rsqf(r2);
@@ -146,6 +147,8 @@ __global__ void __launch_bounds__(256) k_vjp_simple(const DevBox *boxes,
     const float cA = B.cA, cB = B.cB, cC2 = 2.0f * B.cC, cC = B.cC;
     const float eps2 = B.eps * B.eps;
     const bool fast = B.outer_newton != 0;
+    const bool plummer = B.plummer != 0;
+    const float floor2 = B.r2floor;
     Acc3 a;
     for (int dx = -2; dx <= 2; ++dx) {
         const int nx = wrap(cx + dx, K);
@@ -156,14 +159,16 @@ __global__ void __launch_bounds__(256) k_vjp_simple(const DevBox *boxes,
                 const int nc = row + wrap(cz + dz, K);
                 const int j0 = max(cs[nc], 0), j1 = min(cs[nc + 1], B.n);
                 const float sx = oi.x - (float)dx, sy = oi.y - (float)dy, sz = oi.z - (float)dz;
-                const bool outer = fast && (dx == -2 || dx == 2 || dy == -2 || dy == 2 ||
-                                            dz == -2 || dz == 2);
+                // f = q^3 for the outer shell (eps <= 1) and for every pair of
+                // the Plummer law (whose eps_p^2 is in the r^2 floor)
+                const bool outer = plummer || (fast && (dx == -2 || dx == 2 || dy == -2 ||
+                                                        dy == 2 || dz == -2 || dz == 2));
                 for (int j = j0; j < j1; ++j) {
                     const float4 oj = off[j];
                     const float4 vj = cv[j];
                     const float rx = oj.x - sx, ry = oj.y - sy, rz = oj.z - sz;
                     const float ux = vj.x - vi.x, uy = vj.y - vi.y, uz = vj.z - vi.z;
-                    float r2 = __builtin_fmaf(rx, rx, kTiny);
+                    float r2 = __builtin_fmaf(rx, rx, floor2);
                     r2 = __builtin_fmaf(ry, ry, r2);
                     r2 = __builtin_fmaf(rz, rz, r2);
                     const float q = __builtin_amdgcn_rsqf(r2);

@@ -191,7 +191,7 @@ int check_ws(const Layout &L, void *ws, size_t ws_bytes) {
     return NF_OK;
 }
 
-void fill_geometry(const nf_box &B, const Layout &L, int b, DevBox &d) {
+void fill_geometry(const nf_box &B, const Layout &L, int b, DevBox &d, bool plummer = false) {
     std::memset(&d, 0, sizeof d);
     d.n = (int32_t)B.n;
     d.K = B.K;
@@ -205,6 +205,8 @@ void fill_geometry(const nf_box &B, const Layout &L, int b, DevBox &d) {
     d.cB = (float)(-15.0 / (eps * eps * eps * eps));
     d.cC = (float)(6.0 / (eps * eps * eps * eps * eps));
     d.outer_newton = eps <= 1.0 ? 1 : 0;
+    d.plummer = plummer ? 1 : 0;
+    d.r2floor = plummer ? (float)(eps * eps) : kR2Floor;
     d.dense_min = B.dense_min ? B.dense_min : kDefaultDenseMin;
     d.pos = B.pos;
     d.off = reinterpret_cast<float4 *>(B.off);
@@ -295,7 +297,8 @@ static int force_common(int nbox, const nf_box *boxes, double gm, uint32_t flags
     int rc = validate(nbox, boxes, L);
     if (rc) return rc;
     if (!std::isfinite(gm)) return fail(NF_EINVAL, "gm must be finite");
-    if (flags & ~(uint32_t)(NF_COMPENSATED | NF_SIMPLE)) return fail(NF_EINVAL, "unknown flag bits");
+    if (flags & ~(uint32_t)(NF_COMPENSATED | NF_SIMPLE | NF_PLUMMER))
+        return fail(NF_EINVAL, "unknown flag bits");
     if (!out) return fail(NF_EINVAL, "output pointer array is NULL");
     if (vjp && !cot) return fail(NF_EINVAL, "cotangent pointer array is NULL");
     for (int b = 0; b < nbox; ++b) {
@@ -307,7 +310,7 @@ static int force_common(int nbox, const nf_box *boxes, double gm, uint32_t flags
     if ((rc = check_device(why))) return fail(rc, why);
     std::vector<DevBox> tab((size_t)nbox);
     for (int b = 0; b < nbox; ++b) {
-        fill_geometry(boxes[b], L, b, tab[b]);
+        fill_geometry(boxes[b], L, b, tab[b], (flags & NF_PLUMMER) != 0);
         const double k = tab[b].kappa;
         tab[b].scale = (float)(vjp ? gm * k * k * k : gm * k * k);
         tab[b].out = out[b];

@@ -9,6 +9,10 @@ namespace nf {
 
 // Radix sort geometry: 8-bit digits, 256 threads per block, 16 keys per thread.
 constexpr int kDefaultDenseMin = 33;   // nf_box.dense_min == 0
+// Smallest float added to r^2 for Eq. 2: keeps rsq finite for coincident
+// pairs, whose force is then min(poly, inf) * 0 = 0, and is far below half an
+// ulp of any separation that floats resolve between offsets of order one.
+constexpr float kR2Floor = 1.0e-30f;
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kSortThreads = 256;
@@ -28,7 +32,7 @@ struct DevBox {
     int32_t n;            // particles
     int32_t K;            // cells per side
     int32_t ncell;        // K^3
-    int32_t pad0;
+    int32_t plummer;      // 1: Plummer law for every pair (eps = eps_p), 0: Eq. 2
     int64_t base;         // first element of this box in the concatenated arrays
     int64_t cellbase;     // first key of this box in the concatenated key space
     double kappa;         // K / L (cells per length unit), double
@@ -39,6 +43,8 @@ struct DevBox {
     int32_t dense_min;    // cells with at least this many particles take the dense path
     int32_t outer_newton; // 1 when eps <= 1: every pair from the outer shell of
                           // the 5x5x5 block is at r >= 1 >= eps (Newton branch)
+    float r2floor;        // added to r^2: 1e-30 for Eq. 2 (a coincident pair then
+                          // gives 0), eps_p^2 for the Plummer law
     // caller buffers
     const double *pos;    // [n][3]
     float4 *off;          // [n] sorted offsets

@@ -38,7 +38,6 @@ constexpr int kQueueStride = 32;     // words between queue counters (own 128-by
 constexpr int kLightWaves = 4;       // waves sharing one light item
 constexpr int kLightThreads = 64 * kLightWaves;
 constexpr int kRows = 25;            // (dx, dy) rows of the 5x5x5 block
-constexpr float kTinyT = 1.0e-30f;   // floor on r^2: a coincident pair gives 0
 constexpr int kFlush = 32;           // compensated mode: plain partials of <= 32 terms
 
 __device__ __forceinline__ int wrapk(int c, int K) { return c < 0 ? c + K : (c >= K ? c - K : c); }
@@ -199,6 +198,7 @@ __device__ __forceinline__ void fold(Acc &a, float px, float py, float pz) {
 
 struct Coef {
     float cA, cB, cC, cC2, eps2;
+    float floor;   // added to r^2 (DevBox::r2floor)
 };
 
 // One pair of the acceleration sum; SPLINE selects the single-min form of
@@ -208,7 +208,7 @@ __device__ __forceinline__ void pair_accel(float sx, float sy, float sz, float x
                                            float zi, const Coef &k, float &px, float &py,
                                            float &pz) {
     const float rx = sx - xi, ry = sy - yi, rz = sz - zi;
-    float r2 = __builtin_fmaf(rx, rx, kTinyT);
+    float r2 = __builtin_fmaf(rx, rx, k.floor);
     r2 = __builtin_fmaf(ry, ry, r2);
     r2 = __builtin_fmaf(rz, rz, r2);
     const float q = __builtin_amdgcn_rsqf(r2);
@@ -235,7 +235,7 @@ __device__ __forceinline__ void pair_vjp(float sx, float sy, float sz, float vx,
                                          float &py, float &pz) {
     const float rx = sx - xi, ry = sy - yi, rz = sz - zi;
     const float ux = vx - vxi, uy = vy - vyi, uz = vz - vzi;
-    float r2 = __builtin_fmaf(rx, rx, kTinyT);
+    float r2 = __builtin_fmaf(rx, rx, k.floor);
     r2 = __builtin_fmaf(ry, ry, r2);
     r2 = __builtin_fmaf(rz, rz, r2);
     const float q = __builtin_amdgcn_rsqf(r2);
@@ -350,8 +350,9 @@ k_dense(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
         const float4 oi = B.off[slot];
         float4 vi = make_float4(0.f, 0.f, 0.f, 0.f);
         if constexpr (MODE == 1) vi = cot_sorted[B.base + slot];
-        const Coef k{B.cA, B.cB, B.cC, 2.0f * B.cC, B.eps * B.eps};
+        const Coef k{B.cA, B.cB, B.cC, 2.0f * B.cC, B.eps * B.eps, B.r2floor};
         const bool fast = B.outer_newton != 0;
+        const bool plummer = B.plummer != 0;   // Plummer law: one branch for every pair
         cfloat *src = (cfloat *)B.off;
         cfloat *cot = (cfloat *)(cot_sorted + B.base);
         // cell ranges of the 125 source cells: lane r < 25 holds row r's five
@@ -380,7 +381,7 @@ k_dense(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
                     const int j1 = min(__builtin_amdgcn_readlane(ce[q], r), B.n);
                     if (j0 >= j1) continue;
                     const float zs = oi.z - (float)dz;
-                    if (!fast || (in_row && dz >= -1 && dz <= 1))
+                    if (!plummer && (!fast || (in_row && dz >= -1 && dz <= 1)))
                         run_scalar<MODE, true, COMP>(src, cot, j0, j1, xs, ys, zs, vi, k, acc);
                     else
                         run_scalar<MODE, false, COMP>(src, cot, j0, j1, xs, ys, zs, vi, k, acc);
@@ -513,7 +514,7 @@ k_light(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
         const int g = min(uni(cs[cell0 + 1]) - s0, kUnit);
 
         // ---- this lane's sink (sink a, source slice b), loaded before the setup
-        const Coef k{B.cA, B.cB, B.cC, 2.0f * B.cC, B.eps * B.eps};
+        const Coef k{B.cA, B.cB, B.cC, 2.0f * B.cC, B.eps * B.eps, B.r2floor};
         const bool fast = B.outer_newton != 0;
         const int P = kLightThreads / g;
         const bool active = lane < g * P;
@@ -689,7 +690,9 @@ k_light(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
                 stage(u0, u1);
             }
             if (active) {
-                const int split = fast ? inner : total;
+                // Eq. 2 branch for [0, split), f = q^3 (Newton, or Plummer
+                // through the r^2 floor) for [split, total)
+                const int split = B.plummer ? 0 : (fast ? inner : total);
                 const int mid = min(max(split, u0), u1) - u0, hi = u1 - u0;
                 if (mid > 0)
                     segment<MODE, true, COMP>(sm.sx, sm.sv, 0, mid, b, P, oi.x, oi.y, oi.z, vi, k,

@@ -5,6 +5,7 @@ the current stream.
 
     b = bin_particles(pos, K, L, eps_s)        # Sec. 2.1 binning
     a = accel(b, gm)                            # Sec. 2.1 + Eq. 2 sum
+    a = accel(b, gm, plummer=True)              # Plummer law (eps read as eps_p)
     g = accel_vjp(b, cot, gm)                   # VJP w.r.t. positions
     a = nearfield_accel(pos, K, L, eps_s, gm)   # autograd-enabled
 """
@@ -17,7 +18,7 @@ from typing import List, Optional, Sequence
 import torch
 
 from . import _lib
-from ._lib import NF_COMPENSATED, NF_SIMPLE, NfBox
+from ._lib import NF_COMPENSATED, NF_PLUMMER, NF_SIMPLE, NfBox
 
 __all__ = [
     "SPLINE_PER_PLUMMER",
@@ -174,8 +175,9 @@ def bin_particles(pos: torch.Tensor, K: int, L: float, eps_s: float,
     return bin_particles_batched([pos], [K], [L], [eps_s], dense_min)
 
 
-def _flags(compensated: bool, simple: bool) -> int:
-    return (NF_COMPENSATED if compensated else 0) | (NF_SIMPLE if simple else 0)
+def _flags(compensated: bool, simple: bool, plummer: bool = False) -> int:
+    return ((NF_COMPENSATED if compensated else 0) | (NF_SIMPLE if simple else 0)
+            | (NF_PLUMMER if plummer else 0))
 
 
 def _ptr_array(tensors: Sequence[torch.Tensor]):
@@ -186,15 +188,16 @@ def _ptr_array(tensors: Sequence[torch.Tensor]):
 
 
 def accel(b: Binned, gm: float = 1.0, *, compensated: bool = False, simple: bool = False,
-          out: Optional[List[torch.Tensor]] = None):
+          plummer: bool = False, out: Optional[List[torch.Tensor]] = None):
     """Near-field accelerations, float32 [n,3] in input order (a list for
-    several boxes)."""
+    several boxes).  ``plummer``: the Plummer law of Sec. 4.3 with each box's
+    softening length read as eps_p, instead of Eq. 2."""
     lib = _lib.load()
     if out is None:
         out = [torch.empty((bx.n, 3), dtype=torch.float32, device=b.device) for bx in b.boxes]
     ptrs = _ptr_array(out)
     with torch.cuda.device(b.device):
-        rc = lib.nf_accel(b.nbox, b.carray(), float(gm), _flags(compensated, simple), ptrs,
+        rc = lib.nf_accel(b.nbox, b.carray(), float(gm), _flags(compensated, simple, plummer), ptrs,
                           ctypes.c_void_p(b.workspace.data_ptr()), b.workspace.numel(),
                           _stream_handle(b.device))
     _lib.check(rc)
@@ -202,7 +205,7 @@ def accel(b: Binned, gm: float = 1.0, *, compensated: bool = False, simple: bool
 
 
 def accel_vjp(b: Binned, cot, gm: float = 1.0, *, compensated: bool = False,
-              simple: bool = False):
+              simple: bool = False, plummer: bool = False):
     """Vector-Jacobian product of the accelerations w.r.t. positions
     (cell assignment held fixed); float32 [n,3] per box."""
     lib = _lib.load()
@@ -215,7 +218,7 @@ def accel_vjp(b: Binned, cot, gm: float = 1.0, *, compensated: bool = False,
             raise ValueError("cotangent must have shape (n, 3)")
     grads = [torch.empty((bx.n, 3), dtype=torch.float32, device=b.device) for bx in b.boxes]
     with torch.cuda.device(b.device):
-        rc = lib.nf_accel_vjp(b.nbox, b.carray(), float(gm), _flags(compensated, simple),
+        rc = lib.nf_accel_vjp(b.nbox, b.carray(), float(gm), _flags(compensated, simple, plummer),
                               _ptr_array(cots), _ptr_array(grads),
                               ctypes.c_void_p(b.workspace.data_ptr()), b.workspace.numel(),
                               _stream_handle(b.device))
@@ -230,25 +233,27 @@ class NearFieldAccel(torch.autograd.Function):
     forward pass held fixed."""
 
     @staticmethod
-    def forward(ctx, pos, K, L, eps_s, gm, compensated):
+    def forward(ctx, pos, K, L, eps_s, gm, compensated, plummer=False):
         b = bin_particles(pos, K, L, eps_s)
-        a = accel(b, gm, compensated=compensated)
+        a = accel(b, gm, compensated=compensated, plummer=plummer)
         ctx.binned = b
         ctx.gm = gm
         ctx.compensated = compensated
+        ctx.plummer = plummer
         ctx.pos_dtype = pos.dtype
         return a
 
     @staticmethod
     @torch.autograd.function.once_differentiable
     def backward(ctx, grad_acc):
-        g = accel_vjp(ctx.binned, grad_acc, ctx.gm, compensated=ctx.compensated)
-        return g.to(ctx.pos_dtype), None, None, None, None, None
+        g = accel_vjp(ctx.binned, grad_acc, ctx.gm, compensated=ctx.compensated,
+                      plummer=ctx.plummer)
+        return g.to(ctx.pos_dtype), None, None, None, None, None, None
 
 
 def nearfield_accel(pos: torch.Tensor, K: int, L: float, eps_s: float, gm: float = 1.0,
-                    compensated: bool = False) -> torch.Tensor:
-    return NearFieldAccel.apply(pos, K, L, eps_s, gm, compensated)
+                    compensated: bool = False, plummer: bool = False) -> torch.Tensor:
+    return NearFieldAccel.apply(pos, K, L, eps_s, gm, compensated, plummer)
 
 
 class CapturedForce:
@@ -261,19 +266,22 @@ class CapturedForce:
     step is one graph launch."""
 
     def __init__(self, positions: Sequence[torch.Tensor], Ks, Ls, eps, gm: float = 1.0,
-                 compensated: bool = False):
+                 compensated: bool = False, plummer: bool = False):
         self.positions = [_prep_pos(p) for p in positions]
         self.gm = float(gm)
         self.compensated = bool(compensated)
+        self.plummer = bool(plummer)
         self.binned = bin_particles_batched(self.positions, Ks, Ls, eps)
         self.out = [torch.empty((bx.n, 3), dtype=torch.float32, device=self.binned.device)
                     for bx in self.binned.boxes]
-        accel(self.binned, self.gm, compensated=self.compensated, out=self.out)   # warm up
+        accel(self.binned, self.gm, compensated=self.compensated, plummer=self.plummer,
+                  out=self.out)   # warm up
         torch.cuda.synchronize(self.binned.device)
         self.graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(self.graph):
             rebin(self.binned)
-            accel(self.binned, self.gm, compensated=self.compensated, out=self.out)
+            accel(self.binned, self.gm, compensated=self.compensated, plummer=self.plummer,
+                  out=self.out)
 
     def replay(self) -> List[torch.Tensor]:
         self.graph.replay()

@@ -280,6 +280,46 @@ def test_tile_choice_dense_min(dense_min):
     assert err_stats(g, refg)["rms"] <= TOL_PLAIN
 
 
+@pytest.mark.parametrize("simple", [False, True])
+@pytest.mark.parametrize("name", ["uniform32k", "clustered262k"])
+def test_plummer_accel_and_vjp(name, simple):
+    """The Plummer law (Sec. 4.3) on both kernel paths: plain and compensated
+    accelerations and the compensated VJP against the oracle's Plummer law,
+    with eps_p = eps_s / 2.16 (the paper's equal-dynamical-time length)."""
+    sp = WORKLOADS[name]
+    pos = make_box(sp)
+    eps_p = sp.eps_s / nfp.SPLINE_PER_PLUMMER
+    print(f"[plummer] {name} simple={simple}", flush=True)
+    b = nfp.bin_particles(_gpu(pos), sp.K, sp.L, eps_p)
+    ref = oracle.accel(pos, sp.K, sp.L, eps_p, law="plummer")
+    for comp in (False, True):
+        got = nfp.accel(b, 1.0, compensated=comp, simple=simple, plummer=True)
+        st = err_stats(got.cpu().numpy().astype(np.float64), ref)
+        print(name, simple, comp, st)
+        assert st["rms"] <= (TOL_COMP if comp else TOL_PLAIN), st
+    v = gaussian_cotangent(sp.n, 91).astype(np.float32)
+    g = nfp.accel_vjp(b, torch.from_numpy(v).to(DEV), 1.0, compensated=True, simple=simple,
+                      plummer=True).cpu().numpy()
+    refg = oracle.jvp(pos, sp.K, sp.L, eps_p, v.astype(np.float64), law="plummer")
+    assert err_stats(g, refg)["rms"] <= TOL_PLAIN
+
+
+def test_plummer_large_softening_and_autograd():
+    """eps_p above a cell width (the Plummer law has no branch to skip) and
+    the autograd path with plummer=True."""
+    K, L = 8, 1.0
+    pos = clustered_box(4000, 16, K, L, 1.5, 0.5, seed=78)
+    eps = 1.3 * L / K
+    ref = oracle.accel(pos, K, L, eps, law="plummer")
+    p = _gpu(pos).requires_grad_(True)
+    a = nfp.nearfield_accel(p, K, L, eps, 1.0, compensated=True, plummer=True)
+    assert err_stats(a.detach().cpu().numpy().astype(np.float64), ref)["rms"] <= TOL_COMP
+    v = gaussian_cotangent(len(pos), 79).astype(np.float32)
+    (a * torch.from_numpy(v).to(DEV)).sum().backward()
+    refg = oracle.jvp(pos, K, L, eps, v.astype(np.float64), law="plummer")
+    assert err_stats(p.grad.cpu().numpy(), refg)["rms"] <= TOL_PLAIN
+
+
 def test_tile_large_softening_uses_spline_everywhere():
     """eps above one cell width: the outer-shell Newton shortcut must be off."""
     K, L = 8, 1.0
