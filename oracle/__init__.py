@@ -17,3 +17,4 @@ from .oracle import (  # noqa: F401
     set_num_threads,
 )
 from .brute import brute_accel  # noqa: F401
+from .multipoles import abs_moments, multipoles, terms  # noqa: F401
