@@ -85,6 +85,9 @@ enum {
 /* Upper bound on boxes per call. */
 #define NF_MAX_BOXES 4096
 
+/* Highest multipole order of nf_multipoles. */
+#define NF_MAX_ORDER 8
+
 /*
  * One periodic box.  Layouts:
  *   pos         [n][3] double, caller (input) order.  Read by nf_bin_particles.
@@ -175,6 +178,24 @@ int nf_accel(int nbox, const nf_box *boxes, double gm, uint32_t flags,
 int nf_accel_vjp(int nbox, const nf_box *boxes, double gm, uint32_t flags,
                  const float *const *cot, float *const *grad, void *ws,
                  size_t ws_bytes, void *stream);
+
+/*
+ * Per-cell multipole moments of the binned particles (Sec. 2.1: computed for
+ * every cell after the binning, double precision inside, float storage;
+ * p = 8 is the paper's usual order).  Basis (the paper does not fix one):
+ * complete Cartesian moments about the cell centre,
+ *   M_abc(cell) = sum_{i in cell} x_i^a y_i^b z_i^c,   a + b + c <= order,
+ * of the cell offsets in cell widths (the float offsets of nf_bin_particles,
+ * widened to double; products and sums in double, each moment rounded once
+ * to float).  mom: nbox device pointers, each to [K_b^3][T] float with
+ * T = (order+1)(order+2)(order+3)/6, cells in linear order (cx*K + cy)*K + cz,
+ * terms by degree n = a+b+c, then a descending, then b descending.  Every
+ * cell is written (0 for an empty cell).  0 <= order <= NF_MAX_ORDER.
+ * Requires the boxes as filled by nf_bin_particles (off, cell_start).
+ * Work: reads 16 bytes per particle, writes 4 T bytes per cell.
+ */
+int nf_multipoles(int nbox, const nf_box *boxes, int order, float *const *mom, void *ws,
+                  size_t ws_bytes, void *stream);
 
 #ifdef __cplusplus
 }

@@ -22,6 +22,7 @@ NF_SIMPLE = 1 << 1
 NF_PLUMMER = 1 << 2
 
 NF_MAX_BOXES = 4096
+NF_MAX_ORDER = 8
 
 EXPORTED = (
     "nf_version",
@@ -31,6 +32,7 @@ EXPORTED = (
     "nf_bin_particles",
     "nf_accel",
     "nf_accel_vjp",
+    "nf_multipoles",
 )
 
 
@@ -85,6 +87,9 @@ def load():
     lib.nf_accel_vjp.restype = ctypes.c_int
     lib.nf_accel_vjp.argtypes = [ctypes.c_int, P, ctypes.c_double, ctypes.c_uint32,
                                  ctypes.POINTER(vp), ctypes.POINTER(vp), vp, ctypes.c_size_t, vp]
+    lib.nf_multipoles.restype = ctypes.c_int
+    lib.nf_multipoles.argtypes = [ctypes.c_int, P, ctypes.c_int, ctypes.POINTER(vp), vp,
+                                  ctypes.c_size_t, vp]
     _lib = lib
     return lib
 

@@ -369,4 +369,36 @@ int nf_accel_vjp(int nbox, const nf_box *boxes, double gm, uint32_t flags,
     }
 }
 
+int nf_multipoles(int nbox, const nf_box *boxes, int order, float *const *mom, void *ws,
+                  size_t ws_bytes, void *stream) {
+    try {
+        Layout L;
+        int rc = validate(nbox, boxes, L);
+        if (rc) return rc;
+        if (order < 0 || order > NF_MAX_ORDER || order > multipole_max_order())
+            return fail(NF_EINVAL, "order must be in [0, NF_MAX_ORDER]");
+        if (!mom) return fail(NF_EINVAL, "moment pointer array is NULL");
+        for (int b = 0; b < nbox; ++b)
+            if (!mom[b]) return fail(NF_EINVAL, "moment pointer is NULL");
+        if ((rc = check_ws(L, ws, ws_bytes))) return rc;
+        std::string why;
+        if ((rc = check_device(why))) return fail(rc, why);
+        std::vector<DevBox> tab((size_t)nbox);
+        for (int b = 0; b < nbox; ++b) {
+            fill_geometry(boxes[b], L, b, tab[b]);
+            tab[b].out = mom[b];
+        }
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        char *w = static_cast<char *>(ws);
+        DevBox *d_tab = reinterpret_cast<DevBox *>(w + L.table_off);
+        hipError_t e = upload(tab.data(), sizeof(DevBox) * tab.size(), d_tab, s);
+        if (e == hipSuccess) e = multipole_launch(d_tab, nbox, L.max_ncell, order, s);
+        if (e != hipSuccess) return fail(NF_EHIP, std::string("multipoles: ") + hipGetErrorString(e));
+        g_last_error.clear();
+        return NF_OK;
+    } catch (...) {
+        return fail(NF_EINVAL, "internal error");
+    }
+}
+
 }  // extern "C"

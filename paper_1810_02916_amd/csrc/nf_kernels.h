@@ -48,6 +48,12 @@ hipError_t plan_launch(const DevBox *d_boxes, int nbox, const TilePlan &tp, hipS
 hipError_t tile_launch(const DevBox *d_boxes, int mode, bool compensated, const TilePlan &tp,
                        const float4 *cot, hipStream_t s);
 
+// Per-cell multipole moments (nf_multipole.hip).
+int multipole_max_order();
+int multipole_terms(int p);
+hipError_t multipole_launch(const DevBox *d_boxes, int nbox, int64_t max_ncell, int p,
+                            hipStream_t s);
+
 // Force launches.  `items` and `nitems` describe the work list built on the
 // host side of the call (see nf_accel.hip).
 struct ForcePlan {

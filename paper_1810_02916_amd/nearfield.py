@@ -29,6 +29,8 @@ __all__ = [
     "rebin",
     "accel",
     "accel_vjp",
+    "multipole_terms",
+    "multipoles",
     "NearFieldAccel",
     "nearfield_accel",
     "CapturedForce",
@@ -224,6 +226,27 @@ def accel_vjp(b: Binned, cot, gm: float = 1.0, *, compensated: bool = False,
                               _stream_handle(b.device))
     _lib.check(rc)
     return grads[0] if b.nbox == 1 else grads
+
+
+def multipole_terms(order: int) -> int:
+    """Moments per cell at this order: (p+1)(p+2)(p+3)/6."""
+    p = int(order)
+    return (p + 1) * (p + 2) * (p + 3) // 6
+
+
+def multipoles(b: Binned, order: int = 8):
+    """Per-cell Cartesian multipole moments about the cell centres (cell
+    widths), float32 [K^3, T] per box (a list for several boxes); terms by
+    degree, then a descending, then b descending."""
+    lib = _lib.load()
+    T = multipole_terms(order)
+    out = [torch.empty((bx.K ** 3, T), dtype=torch.float32, device=b.device) for bx in b.boxes]
+    with torch.cuda.device(b.device):
+        rc = lib.nf_multipoles(b.nbox, b.carray(), int(order), _ptr_array(out),
+                               ctypes.c_void_p(b.workspace.data_ptr()), b.workspace.numel(),
+                               _stream_handle(b.device))
+    _lib.check(rc)
+    return out[0] if b.nbox == 1 else out
 
 
 class NearFieldAccel(torch.autograd.Function):

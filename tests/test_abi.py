@@ -121,3 +121,17 @@ def test_python_binding_raises_without_gpu_tensors(lib):
     from paper_1810_02916_amd import nearfield
     with pytest.raises(ValueError):
         nearfield.bin_particles(torch.zeros((4, 3), dtype=torch.float64), 8, 1.0, 0.01)
+
+
+def test_multipoles_rejects_bad_arguments(lib):
+    L = lib.load()
+    good = (lib.NfBox * 1)(_box(lib, 10))
+    ws = ctypes.c_void_p(0x100000)
+    outs = (ctypes.c_void_p * 1)(0x2000)
+    assert L.nf_multipoles(1, good, -1, outs, ws, 1 << 20, None) == lib.NF_EINVAL
+    assert L.nf_multipoles(1, good, lib.NF_MAX_ORDER + 1, outs, ws, 1 << 20, None) == lib.NF_EINVAL
+    nulls = (ctypes.c_void_p * 1)(None)
+    assert L.nf_multipoles(1, good, 8, nulls, ws, 1 << 20, None) == lib.NF_EINVAL
+    assert L.nf_multipoles(1, good, 8, None, ws, 1 << 20, None) == lib.NF_EINVAL
+    assert L.nf_multipoles(1, good, 8, outs, None, 1 << 20, None) == lib.NF_EWORKSPACE
+    assert int(re.search(r"#define NF_MAX_ORDER (\d+)", open(HEADER).read()).group(1)) == lib.NF_MAX_ORDER
