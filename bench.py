@@ -36,8 +36,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="clustered2m")
-    ap.add_argument("--cpu-sinks", type=int, default=1 << 18,
-                    help="sinks in the oracle's timed sample")
+    ap.add_argument("--cpu-sinks", type=int, default=0,
+                    help="sinks in the oracle's timed sample (0: every sink of the box)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
@@ -221,6 +221,30 @@ def main():
     achieved = fdom * I / (tdom * 1e-3)
 
     b, a_plain, a_comp, g = out
+
+    # The widened rows, timed after the step (not part of value): the Plummer
+    # law (plain accelerations) and the p = 8 cell multipoles.
+    def timed(fn, reps=args.steps):
+        fn()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+    t_plum = timed(lambda: nfp.accel(b, 1.0, plummer=True))
+    t_mom = timed(lambda: nfp.multipoles(b, 8))
+    mom_bytes = 16.0 * sp.n + 4.0 * nfp.multipole_terms(8) * sp.K ** 3 + 4.0 * (sp.K ** 3 + 1)
+    extras = {
+        "plummer_accel_plain": {"ms": round(t_plum, 4), "gdips": round(I / t_plum / 1e6, 2)},
+        "multipoles_p8": {"ms": round(t_mom, 4), "terms": nfp.multipole_terms(8),
+                          "algorithmic_bytes": int(mom_bytes),
+                          "hbm_gbs": round(mom_bytes / (t_mom * 1e-3) / 1e9, 1),
+                          "hbm_frac": round(mom_bytes / (t_mom * 1e-3) / PEAK_HBM, 4)},
+    }
     result = {
         "metric": "G pair-interactions/s and particles/s (FP32 vs compensated, err vs FP64)",
         "value": round(value, 3),
@@ -256,13 +280,14 @@ def main():
                      "timed": "HIP events around the library call on its stream: planner "
                               "kernels + dense and light force kernels"},
         "kernel_source_hash": kernel_source_hash(),
+        "extras": extras,
     }
 
     if not args.no_cpu:
         import oracle
         from tests.errstats import err_stats
         rng = np.random.default_rng(12345)
-        m = min(args.cpu_sinks, sp.n)
+        m = sp.n if args.cpu_sinks <= 0 else min(args.cpu_sinks, sp.n)
         sinks = np.sort(rng.choice(sp.n, m, replace=False))
         pos_np = pos.cpu().numpy()
         print(f"[bench] oracle on {m} sinks", file=sys.stderr, flush=True)
