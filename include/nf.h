@@ -197,6 +197,36 @@ int nf_accel_vjp(int nbox, const nf_box *boxes, double gm, uint32_t flags,
 int nf_multipoles(int nbox, const nf_box *boxes, int order, float *const *mom, void *ws,
                   size_t ws_bytes, void *stream);
 
+/*
+ * Inputs of the global step choice (Sec. 4.2: the step is bounded by a
+ * largest step in ln a, by eta times the per-cell ratio v_rms / a_max and by
+ * the step in which the fastest particle moves 80% of a cell).  For every
+ * box, from its accelerations and velocities (caller order, [n][3] float) and
+ * its binning:
+ *   amax[b][c] = max_{i in c} |a_i|, vrms[b][c] = sqrt(mean_{i in c} |v_i|^2)
+ *     ([K^3] float each, 0 for an empty cell; the mean velocity is not removed),
+ *   glob[3 b + 0..2] = (max_i |a_i|, sqrt(mean_i |v_i|^2), max_i |v_i|)
+ *     (device double array of 3 nbox values).
+ * Double precision inside, fixed summation order (bitwise reproducible).
+ * The step itself is a host computation on these values.
+ */
+int nf_step_stats(int nbox, const nf_box *boxes, const float *const *acc,
+                  const float *const *vel, float *const *amax, float *const *vrms,
+                  double *glob, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * The step's Kick and Drift stages, kick then drift, in caller order:
+ *   v_i <- float(v_i + kick * a_i)      (evaluated in double, rounded once)
+ *   x_i <- x_i + drift * v_i            (double, with the kicked v_i)
+ * acc: [n][3] float; vel: [n][3] float, updated in place; pos: [n][3] double,
+ * updated in place (it may be the box's pos array; positions are not
+ * wrapped, the next nf_bin_particles wraps them).  kick and drift are the
+ * caller's step factors (time, or the cosmological kick/drift integrals).
+ */
+int nf_kick_drift(int nbox, const nf_box *boxes, const float *const *acc, float *const *vel,
+                  double *const *pos, double kick, double drift, void *ws, size_t ws_bytes,
+                  void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -33,6 +33,8 @@ EXPORTED = (
     "nf_accel",
     "nf_accel_vjp",
     "nf_multipoles",
+    "nf_step_stats",
+    "nf_kick_drift",
 )
 
 
@@ -87,6 +89,12 @@ def load():
     lib.nf_accel_vjp.restype = ctypes.c_int
     lib.nf_accel_vjp.argtypes = [ctypes.c_int, P, ctypes.c_double, ctypes.c_uint32,
                                  ctypes.POINTER(vp), ctypes.POINTER(vp), vp, ctypes.c_size_t, vp]
+    PP = ctypes.POINTER(vp)
+    lib.nf_step_stats.restype = ctypes.c_int
+    lib.nf_step_stats.argtypes = [ctypes.c_int, P, PP, PP, PP, PP, vp, vp, ctypes.c_size_t, vp]
+    lib.nf_kick_drift.restype = ctypes.c_int
+    lib.nf_kick_drift.argtypes = [ctypes.c_int, P, PP, PP, PP, ctypes.c_double, ctypes.c_double,
+                                  vp, ctypes.c_size_t, vp]
     lib.nf_multipoles.restype = ctypes.c_int
     lib.nf_multipoles.argtypes = [ctypes.c_int, P, ctypes.c_int, ctypes.POINTER(vp), vp,
                                   ctypes.c_size_t, vp]

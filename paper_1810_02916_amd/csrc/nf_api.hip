@@ -89,6 +89,7 @@ struct Layout {
     size_t hist_off = 0, cellcnt_off = 0, scan_off = 0;
     size_t cot_off = 0, cellinfo_off = 0, bucket_off = 0, totals_off = 0, dense_off = 0,
            light_off = 0, counter_off = 0;
+    size_t stepio_off = 0, cellstat_off = 0, partial_off = 0;
     int64_t max_dense = 0;
     size_t total = 0;
     int64_t nblk = 0;
@@ -176,7 +177,16 @@ int validate(int nbox, const nf_box *boxes, Layout &L) {
     o = align_up(o + sizeof(Item) * (size_t)(L.C + 16), 256);
     L.counter_off = o;
     o = align_up(o + 4 * (size_t)queue_words(), 256);
-    L.total = std::max(bin_end, o);
+    const size_t force_end = o;
+    // step-statistics scratch, also over the binning scratch region
+    o = scratch0;
+    L.stepio_off = o;
+    o = align_up(o + sizeof(StepIO) * (size_t)nbox, 256);
+    L.cellstat_off = o;
+    o = align_up(o + sizeof(CellStat) * (size_t)L.C, 256);
+    L.partial_off = o;
+    o = align_up(o + sizeof(CellStat) * (size_t)kStepBlocks * (size_t)nbox, 256);
+    L.total = std::max(std::max(bin_end, force_end), o);
     return NF_OK;
 }
 
@@ -364,6 +374,87 @@ int nf_accel_vjp(int nbox, const nf_box *boxes, double gm, uint32_t flags,
                  void *stream) {
     try {
         return force_common(nbox, boxes, gm, flags, cot, grad, ws, ws_bytes, stream, true);
+    } catch (...) {
+        return fail(NF_EINVAL, "internal error");
+    }
+}
+
+// Validation, descriptor and StepIO upload shared by the two stepping calls.
+static int step_common(int nbox, const nf_box *boxes, const std::vector<StepIO> &io, void *ws,
+                       size_t ws_bytes, hipStream_t s, Layout &L, DevBox *&d_tab,
+                       StepIO *&d_io) {
+    if ((int)io.size() != nbox) return fail(NF_EINVAL, "internal error");
+    int rc = check_ws(L, ws, ws_bytes);
+    if (rc) return rc;
+    std::string why;
+    if ((rc = check_device(why))) return fail(rc, why);
+    std::vector<DevBox> tab((size_t)nbox);
+    for (int b = 0; b < nbox; ++b) fill_geometry(boxes[b], L, b, tab[b]);
+    char *w = static_cast<char *>(ws);
+    d_tab = reinterpret_cast<DevBox *>(w + L.table_off);
+    d_io = reinterpret_cast<StepIO *>(w + L.stepio_off);
+    hipError_t e = upload(tab.data(), sizeof(DevBox) * tab.size(), d_tab, s);
+    if (e == hipSuccess) e = upload(io.data(), sizeof(StepIO) * io.size(), d_io, s);
+    if (e != hipSuccess) return fail(NF_EHIP, std::string("upload: ") + hipGetErrorString(e));
+    return NF_OK;
+}
+
+int nf_step_stats(int nbox, const nf_box *boxes, const float *const *acc,
+                  const float *const *vel, float *const *amax, float *const *vrms, double *glob,
+                  void *ws, size_t ws_bytes, void *stream) {
+    try {
+        Layout L;
+        int rc = validate(nbox, boxes, L);
+        if (rc) return rc;
+        if (!acc || !vel || !amax || !vrms || !glob)
+            return fail(NF_EINVAL, "acc, vel, amax, vrms and glob must not be NULL");
+        std::vector<StepIO> io((size_t)nbox);
+        for (int b = 0; b < nbox; ++b) {
+            if (boxes[b].n > 0 && (!acc[b] || !vel[b]))
+                return fail(NF_EINVAL, "acc/vel pointer is NULL");
+            if (!amax[b] || !vrms[b]) return fail(NF_EINVAL, "amax/vrms pointer is NULL");
+            io[b] = StepIO{acc[b], vel[b], nullptr, nullptr, amax[b], vrms[b]};
+        }
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        DevBox *d_tab = nullptr;
+        StepIO *d_io = nullptr;
+        if ((rc = step_common(nbox, boxes, io, ws, ws_bytes, s, L, d_tab, d_io))) return rc;
+        char *w = static_cast<char *>(ws);
+        hipError_t e = step_stats_launch(d_tab, d_io, nbox, L.max_ncell,
+                                         reinterpret_cast<CellStat *>(w + L.cellstat_off),
+                                         reinterpret_cast<CellStat *>(w + L.partial_off), glob, s);
+        if (e != hipSuccess) return fail(NF_EHIP, std::string("step stats: ") + hipGetErrorString(e));
+        g_last_error.clear();
+        return NF_OK;
+    } catch (...) {
+        return fail(NF_EINVAL, "internal error");
+    }
+}
+
+int nf_kick_drift(int nbox, const nf_box *boxes, const float *const *acc, float *const *vel,
+                  double *const *pos, double kick, double drift, void *ws, size_t ws_bytes,
+                  void *stream) {
+    try {
+        Layout L;
+        int rc = validate(nbox, boxes, L);
+        if (rc) return rc;
+        if (!std::isfinite(kick) || !std::isfinite(drift))
+            return fail(NF_EINVAL, "kick and drift must be finite");
+        if (!acc || !vel || !pos) return fail(NF_EINVAL, "acc, vel and pos must not be NULL");
+        std::vector<StepIO> io((size_t)nbox);
+        for (int b = 0; b < nbox; ++b) {
+            if (boxes[b].n > 0 && (!acc[b] || !vel[b] || !pos[b]))
+                return fail(NF_EINVAL, "acc/vel/pos pointer is NULL");
+            io[b] = StepIO{acc[b], nullptr, vel[b], pos[b], nullptr, nullptr};
+        }
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        DevBox *d_tab = nullptr;
+        StepIO *d_io = nullptr;
+        if ((rc = step_common(nbox, boxes, io, ws, ws_bytes, s, L, d_tab, d_io))) return rc;
+        hipError_t e = kick_drift_launch(d_tab, d_io, nbox, L.max_n, kick, drift, s);
+        if (e != hipSuccess) return fail(NF_EHIP, std::string("kick/drift: ") + hipGetErrorString(e));
+        g_last_error.clear();
+        return NF_OK;
     } catch (...) {
         return fail(NF_EINVAL, "internal error");
     }

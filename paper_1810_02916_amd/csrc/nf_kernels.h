@@ -54,6 +54,24 @@ int multipole_terms(int p);
 hipError_t multipole_launch(const DevBox *d_boxes, int nbox, int64_t max_ncell, int p,
                             hipStream_t s);
 
+// Time-step inputs and kick/drift (nf_step.hip).
+struct StepIO {                 // per box, caller order
+    const float *acc;           // [n][3]
+    const float *vel;           // [n][3] (step statistics)
+    float *vel_rw;              // [n][3] (kick)
+    double *pos_rw;             // [n][3] (drift)
+    float *amax, *vrms;         // [K^3] per-cell outputs
+};
+struct CellStat {               // per cell: max |a|, sum |v|^2, max |v|^2
+    double amax, v2sum, vmax2;
+};
+constexpr int kStepBlocks = 256;   // partial reductions per box (power of two)
+hipError_t step_stats_launch(const DevBox *d_boxes, const StepIO *d_io, int nbox,
+                             int64_t max_ncell, CellStat *scratch, CellStat *partial,
+                             double *glob, hipStream_t s);
+hipError_t kick_drift_launch(const DevBox *d_boxes, const StepIO *d_io, int nbox, int64_t max_n,
+                             double kick, double drift, hipStream_t s);
+
 // Force launches.  `items` and `nitems` describe the work list built on the
 // host side of the call (see nf_accel.hip).
 struct ForcePlan {

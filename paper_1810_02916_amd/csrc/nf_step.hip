@@ -1,0 +1,179 @@
+// nf_step.hip -- inputs of the global time-step choice and the leapfrog
+// update (Sec. 4.2: one step for all particles, bounded by a largest step in
+// ln a, by eta times a per-cell v_rms / a_max ratio and by the step at which
+// the fastest particle crosses 80% of a cell; the step's Kick and Drift
+// stages).
+//
+//   k_step_cells   one wave per cell over the cell-sorted slots: a_max and
+//                  v_rms of the cell (double inside, float out) and the
+//                  cell's (a_max, sum |v|^2, max |v|^2) in double scratch;
+//   k_step_partial fixed cell ranges per block -> per-block partials;
+//   k_step_final   one block per box -> (a_max, v_rms, v_max) in double.
+//   k_kick_drift   v <- v + kick * a (double, rounded once to float),
+//                  x <- x + drift * v (double, kicked v), caller order.
+// Every sum has a fixed order (lane-strided, then a fixed butterfly or
+// tree), so the outputs are bitwise reproducible; no multiply-add is fused
+// (contraction is off in these functions, and the products are written as
+// plain operators so that the pragma covers them), so each value is the
+// plain double sequence.
+#include "nf_internal.h"
+#include "nf_kernels.h"
+
+namespace nf {
+namespace {
+
+constexpr int kStatThreads = 256;
+constexpr int kStatWaves = kStatThreads / 64;
+
+__device__ __forceinline__ double dsq3(float x, float y, float z) {
+#pragma clang fp contract(off)
+    const double a = x, b = y, c = z;
+    return (a * a + b * b) + c * c;
+}
+
+// Butterfly over the 64 lanes: every lane ends with the same value (the
+// pairwise sums are commutative, so each level agrees across the pair).
+__device__ __forceinline__ double wave_sum(double x) {
+    for (int o = 32; o >= 1; o >>= 1) x = __dadd_rn(x, __shfl_xor(x, o));
+    return x;
+}
+__device__ __forceinline__ double wave_max(double x) {
+    for (int o = 32; o >= 1; o >>= 1) x = fmax(x, __shfl_xor(x, o));
+    return x;
+}
+
+__global__ void __launch_bounds__(kStatThreads)
+k_step_cells(const DevBox *__restrict__ boxes, const StepIO *__restrict__ io,
+             CellStat *__restrict__ scratch) {
+#pragma clang fp contract(off)
+    const DevBox &B = boxes[blockIdx.y];
+    const StepIO &S = io[blockIdx.y];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int32_t *__restrict__ cs = B.cell_start;
+    for (int c = blockIdx.x * kStatWaves + wave; c < B.ncell; c += gridDim.x * kStatWaves) {
+        const int s0 = cs[c], s1 = cs[c + 1];
+        double am = 0.0, v2 = 0.0, vm = 0.0;
+        for (int s = s0 + lane; s < s1; s += 64) {
+            const int i = B.order[s];
+            if (i < 0 || i >= B.n) continue;   // never taken for a consistent binning
+            const float *a = S.acc + 3 * (int64_t)i;
+            const float *v = S.vel + 3 * (int64_t)i;
+            const double a2 = dsq3(a[0], a[1], a[2]);
+            const double w2 = dsq3(v[0], v[1], v[2]);
+            am = fmax(am, __dsqrt_rn(a2));
+            v2 = v2 + w2;
+            vm = fmax(vm, w2);
+        }
+        am = wave_max(am);
+        v2 = wave_sum(v2);
+        vm = wave_max(vm);
+        if (lane == 0) {
+            const int cnt = s1 - s0;
+            S.amax[c] = (float)am;
+            S.vrms[c] = cnt > 0 ? (float)__dsqrt_rn(__ddiv_rn(v2, (double)cnt)) : 0.0f;
+            scratch[B.cellbase + c] = CellStat{am, v2, vm};
+        }
+    }
+}
+
+// Block b of box y reduces cells [b * chunk, (b + 1) * chunk).
+__global__ void __launch_bounds__(kStatThreads)
+k_step_partial(const DevBox *__restrict__ boxes, const CellStat *__restrict__ scratch,
+               CellStat *__restrict__ partial) {
+    __shared__ CellStat red[kStatThreads];
+    const DevBox &B = boxes[blockIdx.y];
+    const int t = threadIdx.x;
+    const int chunk = (B.ncell + kStepBlocks - 1) / kStepBlocks;
+    const int c0 = blockIdx.x * chunk, c1 = min(B.ncell, c0 + chunk);
+    CellStat r{0.0, 0.0, 0.0};
+    for (int c = c0 + t; c < c1; c += kStatThreads) {
+        const CellStat x = scratch[B.cellbase + c];
+        r.amax = fmax(r.amax, x.amax);
+        r.v2sum = __dadd_rn(r.v2sum, x.v2sum);
+        r.vmax2 = fmax(r.vmax2, x.vmax2);
+    }
+    red[t] = r;
+    __syncthreads();
+    for (int h = kStatThreads / 2; h >= 1; h >>= 1) {
+        if (t < h) {
+            red[t].amax = fmax(red[t].amax, red[t + h].amax);
+            red[t].v2sum = __dadd_rn(red[t].v2sum, red[t + h].v2sum);
+            red[t].vmax2 = fmax(red[t].vmax2, red[t + h].vmax2);
+        }
+        __syncthreads();
+    }
+    if (t == 0) partial[(int64_t)blockIdx.y * kStepBlocks + blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(kStepBlocks)
+k_step_final(const DevBox *__restrict__ boxes, const CellStat *__restrict__ partial,
+             double *__restrict__ glob) {
+    __shared__ CellStat red[kStepBlocks];
+    const DevBox &B = boxes[blockIdx.x];
+    const int t = threadIdx.x;
+    red[t] = partial[(int64_t)blockIdx.x * kStepBlocks + t];
+    __syncthreads();
+    for (int h = kStepBlocks / 2; h >= 1; h >>= 1) {
+        if (t < h) {
+            red[t].amax = fmax(red[t].amax, red[t + h].amax);
+            red[t].v2sum = __dadd_rn(red[t].v2sum, red[t + h].v2sum);
+            red[t].vmax2 = fmax(red[t].vmax2, red[t + h].vmax2);
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        double *g = glob + 3 * (int64_t)blockIdx.x;
+        g[0] = red[0].amax;
+        g[1] = B.n > 0 ? __dsqrt_rn(__ddiv_rn(red[0].v2sum, (double)B.n)) : 0.0;
+        g[2] = __dsqrt_rn(red[0].vmax2);
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_kick_drift(const DevBox *__restrict__ boxes, const StepIO *__restrict__ io, double kick,
+             double drift) {
+#pragma clang fp contract(off)   // the update is a multiply then an add, as defined
+    const DevBox &B = boxes[blockIdx.y];
+    const StepIO &S = io[blockIdx.y];
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < B.n;
+         i += (int64_t)gridDim.x * 256) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double a = S.acc[3 * i + k];
+            const double v = S.vel_rw[3 * i + k];
+            const float vn = (float)(v + kick * a);
+            S.vel_rw[3 * i + k] = vn;
+            S.pos_rw[3 * i + k] = S.pos_rw[3 * i + k] + drift * (double)vn;
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t step_stats_launch(const DevBox *d_boxes, const StepIO *d_io, int nbox,
+                             int64_t max_ncell, CellStat *scratch, CellStat *partial,
+                             double *glob, hipStream_t s) {
+    const int64_t nb = (max_ncell + kStatWaves - 1) / kStatWaves;
+    const unsigned gx = (unsigned)std::max<int64_t>(1, std::min<int64_t>(nb, 8192));
+    hipLaunchKernelGGL(k_step_cells, dim3(gx, (unsigned)nbox), dim3(kStatThreads), 0, s, d_boxes,
+                       d_io, scratch);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_step_partial, dim3(kStepBlocks, (unsigned)nbox), dim3(kStatThreads), 0, s,
+                       d_boxes, (const CellStat *)scratch, partial);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_step_final, dim3((unsigned)nbox), dim3(kStepBlocks), 0, s, d_boxes,
+                       (const CellStat *)partial, glob);
+    return hipGetLastError();
+}
+
+hipError_t kick_drift_launch(const DevBox *d_boxes, const StepIO *d_io, int nbox, int64_t max_n,
+                             double kick, double drift, hipStream_t s) {
+    const int64_t nb = (max_n + 255) / 256;
+    const unsigned gx = (unsigned)std::max<int64_t>(1, std::min<int64_t>(nb, 16384));
+    hipLaunchKernelGGL(k_kick_drift, dim3(gx, (unsigned)nbox), dim3(256), 0, s, d_boxes, d_io,
+                       kick, drift);
+    return hipGetLastError();
+}
+
+}  // namespace nf

@@ -30,6 +30,9 @@ __all__ = [
     "accel",
     "accel_vjp",
     "multipole_terms",
+    "step_stats",
+    "kick_drift",
+    "choose_step",
     "multipoles",
     "NearFieldAccel",
     "nearfield_accel",
@@ -247,6 +250,74 @@ def multipoles(b: Binned, order: int = 8):
                                _stream_handle(b.device))
     _lib.check(rc)
     return out[0] if b.nbox == 1 else out
+
+
+def _f32_list(xs, b: Binned, what: str):
+    xs = [xs] if isinstance(xs, torch.Tensor) else list(xs)
+    if len(xs) != b.nbox:
+        raise ValueError(f"one {what} tensor per box is required")
+    for x, bx in zip(xs, b.boxes):
+        if x.dtype != torch.float32 or not x.is_contiguous() or tuple(x.shape) != (bx.n, 3) \
+                or x.device != b.device:
+            raise ValueError(f"{what} must be contiguous float32 (n, 3) tensors on the boxes' device")
+    return xs
+
+
+def step_stats(b: Binned, acc, vel):
+    """Per-cell a_max and v_rms (float32 [K^3] per box) and the global
+    (a_max, v_rms, v_max) per box (float64 [nbox, 3]), the inputs of the
+    step choice of Sec. 4.2."""
+    lib = _lib.load()
+    accs, vels = _f32_list(acc, b, "acc"), _f32_list(vel, b, "vel")
+    amax = [torch.empty(bx.K ** 3, dtype=torch.float32, device=b.device) for bx in b.boxes]
+    vrms = [torch.empty(bx.K ** 3, dtype=torch.float32, device=b.device) for bx in b.boxes]
+    glob = torch.empty((b.nbox, 3), dtype=torch.float64, device=b.device)
+    with torch.cuda.device(b.device):
+        rc = lib.nf_step_stats(b.nbox, b.carray(), _ptr_array(accs), _ptr_array(vels),
+                               _ptr_array(amax), _ptr_array(vrms), ctypes.c_void_p(glob.data_ptr()),
+                               ctypes.c_void_p(b.workspace.data_ptr()), b.workspace.numel(),
+                               _stream_handle(b.device))
+    _lib.check(rc)
+    if b.nbox == 1:
+        return amax[0], vrms[0], glob[0]
+    return amax, vrms, glob
+
+
+def kick_drift(b: Binned, acc, vel, pos, kick: float, drift: float) -> None:
+    """In place: vel <- vel + kick * acc (float), pos <- pos + drift * vel
+    (float64, kicked vel).  ``pos`` may be the tensor the boxes were binned
+    from; bin again (rebin) before the next force call."""
+    lib = _lib.load()
+    accs, vels = _f32_list(acc, b, "acc"), _f32_list(vel, b, "vel")
+    poss = [pos] if isinstance(pos, torch.Tensor) else list(pos)
+    if len(poss) != b.nbox:
+        raise ValueError("one position tensor per box is required")
+    for p, bx in zip(poss, b.boxes):
+        if p.dtype != torch.float64 or not p.is_contiguous() or tuple(p.shape) != (bx.n, 3) \
+                or p.device != b.device:
+            raise ValueError("pos must be contiguous float64 (n, 3) tensors on the boxes' device")
+    with torch.cuda.device(b.device):
+        rc = lib.nf_kick_drift(b.nbox, b.carray(), _ptr_array(accs), _ptr_array(vels),
+                               _ptr_array(poss), float(kick), float(drift),
+                               ctypes.c_void_p(b.workspace.data_ptr()), b.workspace.numel(),
+                               _stream_handle(b.device))
+    _lib.check(rc)
+
+
+def choose_step(amax, vrms, glob, *, dlna_max: float, hubble: float, eta: float,
+                cell_width: float) -> float:
+    """The step of Sec. 4.2 from one box's statistics: the smallest of
+    dlna_max / hubble, eta * max(global v_rms / a_max, smallest per-cell
+    v_rms / a_max over cells with a_max > 0), and 0.8 cell_width / v_max."""
+    am = amax.double()
+    ok = am > 0
+    cell_ratio = float((vrms.double()[ok] / am[ok]).min()) if bool(ok.any()) else float("inf")
+    g = [float(x) for x in glob]
+    glob_ratio = g[1] / g[0] if g[0] > 0 else float("inf")
+    dt1 = dlna_max / hubble
+    dt2 = eta * max(cell_ratio, glob_ratio)
+    dt3 = 0.8 * cell_width / g[2] if g[2] > 0 else float("inf")
+    return min(dt1, dt2, dt3)
 
 
 class NearFieldAccel(torch.autograd.Function):

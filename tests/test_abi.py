@@ -135,3 +135,19 @@ def test_multipoles_rejects_bad_arguments(lib):
     assert L.nf_multipoles(1, good, 8, None, ws, 1 << 20, None) == lib.NF_EINVAL
     assert L.nf_multipoles(1, good, 8, outs, None, 1 << 20, None) == lib.NF_EWORKSPACE
     assert int(re.search(r"#define NF_MAX_ORDER (\d+)", open(HEADER).read()).group(1)) == lib.NF_MAX_ORDER
+
+
+def test_stepping_calls_reject_bad_arguments(lib):
+    L = lib.load()
+    good = (lib.NfBox * 1)(_box(lib, 10))
+    ws = ctypes.c_void_p(0x100000)
+    p1 = (ctypes.c_void_p * 1)(0x2000)
+    nul = (ctypes.c_void_p * 1)(None)
+    g = ctypes.c_void_p(0x3000)
+    assert L.nf_step_stats(1, good, p1, p1, p1, p1, None, ws, 1 << 20, None) == lib.NF_EINVAL
+    assert L.nf_step_stats(1, good, nul, p1, p1, p1, g, ws, 1 << 20, None) == lib.NF_EINVAL
+    assert L.nf_step_stats(1, good, p1, p1, nul, p1, g, ws, 1 << 20, None) == lib.NF_EINVAL
+    assert L.nf_step_stats(1, good, p1, p1, p1, p1, g, None, 1 << 20, None) == lib.NF_EWORKSPACE
+    assert L.nf_kick_drift(1, good, p1, p1, p1, float("nan"), 0.1, ws, 1 << 20, None) == lib.NF_EINVAL
+    assert L.nf_kick_drift(1, good, p1, p1, nul, 0.1, 0.1, ws, 1 << 20, None) == lib.NF_EINVAL
+    assert L.nf_kick_drift(1, good, p1, p1, p1, 0.1, 0.1, ws, 16, None) == lib.NF_EWORKSPACE
