@@ -90,6 +90,7 @@ struct Layout {
     size_t cot_off = 0, cellinfo_off = 0, bucket_off = 0, totals_off = 0, dense_off = 0,
            light_off = 0, counter_off = 0;
     size_t stepio_off = 0, cellstat_off = 0, partial_off = 0;
+    size_t mp_base_off = 0, mp_first_off = 0, mp_first_bytes = 0;
     int64_t max_dense = 0;
     size_t total = 0;
     int64_t nblk = 0;
@@ -186,7 +187,18 @@ int validate(int nbox, const nf_box *boxes, Layout &L) {
     o = align_up(o + sizeof(CellStat) * (size_t)L.C, 256);
     L.partial_off = o;
     o = align_up(o + sizeof(CellStat) * (size_t)kStepBlocks * (size_t)nbox, 256);
-    L.total = std::max(std::max(bin_end, force_end), o);
+    const size_t step_end = o;
+    // multipole partition, also over the binning scratch region
+    o = scratch0;
+    L.mp_base_off = o;
+    o = align_up(o + 8 * ((size_t)nbox + 1), 256);
+    L.mp_first_off = o;
+    int64_t nranges = 0;
+    for (int b = 0; b < nbox; ++b)
+        nranges += multipole_ranges(boxes[b].n, (int64_t)boxes[b].K * boxes[b].K * boxes[b].K) + 1;
+    L.mp_first_bytes = 4 * (size_t)nranges;
+    o = align_up(o + L.mp_first_bytes, 256);
+    L.total = std::max(std::max(std::max(bin_end, force_end), step_end), o);
     return NF_OK;
 }
 
@@ -475,15 +487,26 @@ int nf_multipoles(int nbox, const nf_box *boxes, int order, float *const *mom, v
         std::string why;
         if ((rc = check_device(why))) return fail(rc, why);
         std::vector<DevBox> tab((size_t)nbox);
+        std::vector<int64_t> rbase((size_t)nbox + 1, 0);
+        int64_t max_ranges = 1;
         for (int b = 0; b < nbox; ++b) {
             fill_geometry(boxes[b], L, b, tab[b]);
             tab[b].out = mom[b];
+            const int64_t r = multipole_ranges(boxes[b].n, (int64_t)tab[b].ncell);
+            rbase[b + 1] = rbase[b] + r;
+            max_ranges = std::max(max_ranges, r);
         }
+        if (max_ranges > INT32_MAX || (size_t)(rbase[nbox] + nbox) * 4 > L.mp_first_bytes)
+            return fail(NF_EUNSUPPORTED, "multipole partition exceeds the workspace plan");
         hipStream_t s = static_cast<hipStream_t>(stream);
         char *w = static_cast<char *>(ws);
         DevBox *d_tab = reinterpret_cast<DevBox *>(w + L.table_off);
+        int64_t *d_rbase = reinterpret_cast<int64_t *>(w + L.mp_base_off);
+        int32_t *d_first = reinterpret_cast<int32_t *>(w + L.mp_first_off);
         hipError_t e = upload(tab.data(), sizeof(DevBox) * tab.size(), d_tab, s);
-        if (e == hipSuccess) e = multipole_launch(d_tab, nbox, L.max_ncell, order, s);
+        if (e == hipSuccess) e = upload(rbase.data(), sizeof(int64_t) * rbase.size(), d_rbase, s);
+        if (e == hipSuccess)
+            e = multipole_launch(d_tab, nbox, L.max_ncell, max_ranges, d_rbase, d_first, order, s);
         if (e != hipSuccess) return fail(NF_EHIP, std::string("multipoles: ") + hipGetErrorString(e));
         g_last_error.clear();
         return NF_OK;

@@ -51,8 +51,13 @@ hipError_t tile_launch(const DevBox *d_boxes, int mode, bool compensated, const 
 // Per-cell multipole moments (nf_multipole.hip).
 int multipole_max_order();
 int multipole_terms(int p);
-hipError_t multipole_launch(const DevBox *d_boxes, int nbox, int64_t max_ncell, int p,
-                            hipStream_t s);
+// Workgroup ranges of one box (n particles, ncell cells).
+int64_t multipole_ranges(int64_t n, int64_t ncell);
+// d_range_base: [nbox + 1] prefix of the boxes' range counts; d_first:
+// sum over boxes of (ranges + 1) int32.
+hipError_t multipole_launch(const DevBox *d_boxes, int nbox, int64_t max_ncell,
+                            int64_t max_ranges, const int64_t *d_range_base, int32_t *d_first,
+                            int p, hipStream_t s);
 
 // Time-step inputs and kick/drift (nf_step.hip).
 struct StepIO {                 // per box, caller order
