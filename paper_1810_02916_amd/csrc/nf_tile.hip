@@ -1,19 +1,20 @@
 // nf_tile.hip -- tiled near-field kernels for gfx950: a device-side planner
-// that cuts the cell grid into work items, and two persistent one-wave-per-
-// workgroup kernels that sum the pair forces of Eq. 2 (Sec. 4.3) over the
-// 5x5x5 cell block of Sec. 2.1.
+// that cuts the cell grid into work items, and two persistent kernels that
+// sum the pair forces of Eq. 2 (Sec. 4.3) over the 5x5x5 cell block of
+// Sec. 2.1.
 //
-// Work items (one wave each):
-//   * dense  -- 64 sinks (or the remainder) of a cell holding at least
-//               dense_min particles (33 by default).  One sink per lane; every lane needs the same
-//               source at the same time, so sources are read from the
-//               cell-sorted array with scalar loads and enter the arithmetic
-//               as SGPR operands, and the sink is shifted into each source
-//               cell's frame.  No LDS, so many waves fit on a CU and hide the
-//               load latency.  Items run heaviest neighbourhood first.
-//   * light  -- all sinks of a cell holding fewer particles (at most 64), one
-//               item per 4-wave workgroup.  The 125 source
-//               cells are staged in LDS in the sink cell's own frame,
+// The sinks of a cell are cut into chunks of 64.  Work items:
+//   * dense  -- a full 64-sink chunk, or the last chunk when it holds at
+//               least dense_min sinks (33 by default); one wave per item, one
+//               sink per lane.  Every lane needs the same source at the same
+//               time, so sources are read from the cell-sorted array with
+//               scalar loads and enter the arithmetic as SGPR operands, and
+//               the sink is shifted into each source cell's frame.  No LDS, so
+//               many waves fit on a CU and hide the load latency.  Items run
+//               heaviest neighbourhood first.
+//   * light  -- a smaller last chunk (all sinks of a cell of fewer than
+//               dense_min particles), one item per 4-wave workgroup.  The 125
+//               source cells are staged in LDS in the sink cell's own frame,
 //               (o_x + dx, o_y + dy, o_z + dz), the 27 cells with |d| <= 1
 //               first, then the 98 outer cells, so the sum is two contiguous
 //               segments; the g sinks are spread over the 256 threads as
@@ -22,7 +23,8 @@
 // In both paths a source of the sink's own cell is used unshifted, so the
 // closest pairs are formed from the exact float offsets, and a cell of the
 // outer shell of the block (some |d| = 2) is at r >= 1 and takes the Newton
-// branch directly when eps <= 1.
+// branch directly when eps <= 1.  The Plummer law is the Newton branch with
+// eps_p^2 as the floor on r^2, for every pair.
 #include <climits>
 
 #include "nf_internal.h"
