@@ -5,7 +5,7 @@
 //
 // The sinks of a cell are cut into chunks of 64.  Work items:
 //   * dense  -- a full 64-sink chunk, or the last chunk when it holds at
-//               least dense_min sinks (33 by default); one wave per item, one
+//               least dense_min sinks (25 by default); one wave per item, one
 //               sink per lane.  Every lane needs the same source at the same
 //               time, so sources are read from the cell-sorted array with
 //               scalar loads and enter the arithmetic as SGPR operands, and
@@ -473,7 +473,7 @@ __device__ __forceinline__ void segment(const float4 *__restrict__ sx, const flo
 }
 
 template <int MODE, bool COMP, int CAP>
-__global__ void __launch_bounds__(kLightThreads) __attribute__((amdgpu_waves_per_eu(MODE == 0 ? 8 : 6)))
+__global__ void __launch_bounds__(kLightThreads) __attribute__((amdgpu_waves_per_eu(MODE == 0 ? 8 : 7)))
 k_light(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
         const uint32_t *__restrict__ totals, uint32_t *counter,
         const float4 *__restrict__ cot_sorted) {
