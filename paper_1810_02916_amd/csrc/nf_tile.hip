@@ -243,21 +243,28 @@ __device__ __forceinline__ void pair_vjp(float sx, float sy, float sz, float vx,
     const float q = __builtin_amdgcn_rsqf(r2);
     const float q2 = q * q;
     const float q3 = q2 * q;
-    float g = q3, h = -3.0f * q3 * q2;
+    float rdu = rx * ux;
+    rdu = __builtin_fmaf(ry, uy, rdu);
+    rdu = __builtin_fmaf(rz, uz, rdu);
     if constexpr (SPLINE) {
+        float g = q3, h = -3.0f * q3 * q2;
         if (r2 < k.eps2) {
             const float rho = r2 * q;
             g = __builtin_fmaf(__builtin_fmaf(k.cC, rho, k.cB), rho, k.cA);
             h = __builtin_fmaf(k.cB, q, k.cC2);
         }
+        const float t = h * rdu;
+        px = __builtin_fmaf(t, rx, __builtin_fmaf(g, ux, px));
+        py = __builtin_fmaf(t, ry, __builtin_fmaf(g, uy, py));
+        pz = __builtin_fmaf(t, rz, __builtin_fmaf(g, uz, pz));
+    } else {
+        // Newton (or Plummer through the r^2 floor): g u + h (r.u) r with
+        // g = q^3, h = -3 q^5 is q^3 (u - 3 q^2 (r.u) r): 23 VALU
+        const float w = (-3.0f * q2) * rdu;
+        px = __builtin_fmaf(q3, __builtin_fmaf(w, rx, ux), px);
+        py = __builtin_fmaf(q3, __builtin_fmaf(w, ry, uy), py);
+        pz = __builtin_fmaf(q3, __builtin_fmaf(w, rz, uz), pz);
     }
-    float rdu = rx * ux;
-    rdu = __builtin_fmaf(ry, uy, rdu);
-    rdu = __builtin_fmaf(rz, uz, rdu);
-    const float t = h * rdu;
-    px = __builtin_fmaf(t, rx, __builtin_fmaf(g, ux, px));
-    py = __builtin_fmaf(t, ry, __builtin_fmaf(g, uy, py));
-    pz = __builtin_fmaf(t, rz, __builtin_fmaf(g, uz, pz));
 }
 
 // Final value of a lane's sum (compensation folded in).
