@@ -26,6 +26,8 @@
 // branch directly when eps <= 1.  The Plummer law is the Newton branch with
 // eps_p^2 as the floor on r^2, for every pair.
 #include <climits>
+#include <mutex>
+#include <vector>
 
 #include "nf_internal.h"
 #include "nf_kernels.h"
@@ -778,6 +780,35 @@ int persistent_grid(Kern kern, int threads) {
     return std::max(1, ncu) * std::max(1, per);
 }
 
+// The dense and light kernels of one call run concurrently: the light kernel
+// goes to a library stream of the same device (default priority), forked from
+// and joined back to the caller's stream with events, so the two kernels
+// share the CUs (the dense kernel uses no LDS, the light kernel little VALU
+// latency hiding of its own) and neither's tail is exposed.  Under graph
+// capture the fork and join become graph dependencies.  The sequence is
+// enqueued under a lock: the events are shared by all calls on the device.
+struct SideStream {
+    hipStream_t s = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+std::mutex g_side_mu;
+std::vector<SideStream> g_side;
+
+hipError_t side_stream(SideStream &out) {   // caller holds g_side_mu
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if ((int)g_side.size() <= dev) g_side.resize(dev + 1);
+    SideStream &ss = g_side[dev];
+    if (!ss.s) {
+        if ((e = hipStreamCreateWithFlags(&ss.s, hipStreamNonBlocking)) != hipSuccess) return e;
+        if ((e = hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming)) != hipSuccess) return e;
+        if ((e = hipEventCreateWithFlags(&ss.join, hipEventDisableTiming)) != hipSuccess) return e;
+    }
+    out = ss;
+    return hipSuccess;
+}
+
 template <int MODE, bool COMP>
 hipError_t launch_force(const DevBox *d_boxes, const TilePlan &tp, const float4 *cot,
                         hipStream_t s) {
@@ -787,14 +818,21 @@ hipError_t launch_force(const DevBox *d_boxes, const TilePlan &tp, const float4 
     static const int gl =
         (persistent_grid(k_light<MODE, COMP, CAP>, kLightThreads) + kQueues - 1) / kQueues *
         kQueues;
+    std::lock_guard<std::mutex> lk(g_side_mu);
+    SideStream ss;
+    hipError_t e = side_stream(ss);
+    if (e != hipSuccess) return e;
+    if ((e = hipEventRecord(ss.fork, s)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(ss.s, ss.fork, 0)) != hipSuccess) return e;
+    hipLaunchKernelGGL((k_light<MODE, COMP, CAP>), dim3(gl), dim3(kLightThreads), 0, ss.s,
+                       d_boxes, (const Item *)tp.light, (const uint32_t *)tp.totals,
+                       tp.counter + kQueueStride, cot);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = hipEventRecord(ss.join, ss.s)) != hipSuccess) return e;
     hipLaunchKernelGGL((k_dense<MODE, COMP>), dim3(gd), dim3(kUnit), 0, s, d_boxes,
                        (const Item *)tp.dense, (const uint32_t *)tp.totals, tp.counter, cot);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_light<MODE, COMP, CAP>), dim3(gl), dim3(kLightThreads), 0, s, d_boxes,
-                       (const Item *)tp.light, (const uint32_t *)tp.totals,
-                       tp.counter + kQueueStride, cot);
-    return hipGetLastError();
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return hipStreamWaitEvent(s, ss.join, 0);
 }
 
 }  // namespace
