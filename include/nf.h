@@ -115,7 +115,7 @@ typedef struct nf_box {
                            64; a chunk of at least dense_min sinks is summed one
                            sink per lane (sources broadcast), a smaller one is
                            spread over (sink, source-slice) lanes.  0 picks the
-                           library default (25); otherwise 2..65.  The workspace
+                           library default (41); otherwise 2..65.  The workspace
                            size depends on it (it grows as dense_min falls). */
     double L;
     double eps_s;

@@ -8,7 +8,7 @@
 namespace nf {
 
 // Radix sort geometry: 8-bit digits, 256 threads per block, 16 keys per thread.
-constexpr int kDefaultDenseMin = 25;   // nf_box.dense_min == 0
+constexpr int kDefaultDenseMin = 41;   // nf_box.dense_min == 0
 // Smallest float added to r^2 for Eq. 2: keeps rsq finite for coincident
 // pairs, whose force is then min(poly, inf) * 0 = 0, and is far below half an
 // ulp of any separation that floats resolve between offsets of order one.

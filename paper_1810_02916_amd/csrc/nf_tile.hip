@@ -5,7 +5,7 @@
 //
 // The sinks of a cell are cut into chunks of 64.  Work items:
 //   * dense  -- a full 64-sink chunk, or the last chunk when it holds at
-//               least dense_min sinks (25 by default); one wave per item, one
+//               least dense_min sinks (41 by default); one wave per item, one
 //               sink per lane.  Every lane needs the same source at the same
 //               time, so sources are read from the cell-sorted array with
 //               scalar loads and enter the arithmetic as SGPR operands, and
