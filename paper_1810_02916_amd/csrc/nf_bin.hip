@@ -27,7 +27,7 @@ __global__ void k_bin_zero_status(const DevBox *boxes, int nbox) {
 // ------------------------------------------------------------- cell keys
 
 // One thread per particle: linear cell id (in the box's key range) and its
-// concatenated element index; atomically counts particles per cell.
+// concatenated element index.
 __global__ void __launch_bounds__(256) k_bin_keys(const DevBox *boxes, BinScratch sc) {
     const DevBox &B = boxes[blockIdx.y];
     int i = blockIdx.x * 256 + threadIdx.x;
@@ -47,7 +47,6 @@ __global__ void __launch_bounds__(256) k_bin_keys(const DevBox *boxes, BinScratc
     int64_t g = B.base + i;
     sc.keys[0][g] = key;
     sc.vals[0][g] = (uint32_t)g;
-    atomicAdd(&sc.cellcnt[key], 1u);
 }
 
 // ------------------------------------------------------------- radix sort
@@ -199,10 +198,27 @@ k_scan_down(const uint32_t *in, uint32_t *out, int64_t M, const uint32_t *__rest
     }
 }
 
+// ------------------------------------------------------------- cell starts
+
+// first[k] = the first sorted slot whose key is >= k, for k = 0 .. C (the
+// exclusive scan of the cell counts), from the sorted keys: slot s writes
+// the keys in (key[s-1], key[s]], slot N the keys after the last one.  Keys
+// are non-decreasing, so every k is written exactly once; no atomics.
+__global__ void __launch_bounds__(256)
+k_cell_first(const uint32_t *__restrict__ keys, int64_t N, int64_t C,
+             uint32_t *__restrict__ first) {
+    for (int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x; s <= N;
+         s += (int64_t)gridDim.x * 256) {
+        const int64_t lo = s == 0 ? 0 : (int64_t)keys[s - 1] + 1;
+        const int64_t hi = s == N ? C : (int64_t)keys[s];
+        for (int64_t k = lo; k <= hi; ++k) first[k] = (uint32_t)s;
+    }
+}
+
 // ------------------------------------------------------------- finish
 
-// Per box: cell_start from the scanned cell counts, order from the sorted
-// element indices, and the float offsets recomputed from the positions.
+// Per box: cell_start from the first slots of its cells, order from the
+// sorted element indices, and the float offsets recomputed from the positions.
 __global__ void __launch_bounds__(256)
 k_bin_finish(const DevBox *boxes, const uint32_t *__restrict__ cellscan,
              const uint32_t *__restrict__ vals_sorted) {
@@ -270,8 +286,6 @@ hipError_t fill_u32(uint32_t *p, int64_t count, uint32_t value, hipStream_t s) {
 
 hipError_t bin_launch(const DevBox *d_boxes, int nbox, const BinPlan &p, hipStream_t s) {
     hipError_t e;
-    const unsigned fill_blocks = (unsigned)std::min<int64_t>(4096, (p.C + 1 + 255) / 256 + 1);
-    hipLaunchKernelGGL(k_fill_u32, dim3(fill_blocks), dim3(256), 0, s, p.sc.cellcnt, p.C + 1, 0u);
     hipLaunchKernelGGL(k_bin_zero_status, dim3((nbox + 255) / 256), dim3(256), 0, s, d_boxes, nbox);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (p.N > 0) {
@@ -294,7 +308,11 @@ hipError_t bin_launch(const DevBox *d_boxes, int nbox, const BinPlan &p, hipStre
             src ^= 1;
         }
     }
-    if ((e = scan_exclusive(p.sc.cellcnt, p.C + 1, p.scan_scratch, s)) != hipSuccess) return e;
+    const unsigned first_blocks =
+        (unsigned)std::max<int64_t>(1, std::min<int64_t>(65535, (p.N + 1 + 255) / 256));
+    hipLaunchKernelGGL(k_cell_first, dim3(first_blocks), dim3(256), 0, s,
+                       (const uint32_t *)p.sc.keys[p.passes & 1], p.N, p.C, p.sc.cellcnt);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_bin_finish,
                        dim3((unsigned)((std::max<int64_t>(p.max_n, p.max_ncell + 1) + 255) / 256),
                             (unsigned)nbox),

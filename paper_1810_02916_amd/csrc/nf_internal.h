@@ -68,7 +68,7 @@ struct BinScratch {
     uint32_t *keys[2];    // [N] concatenated keys (cellbase_b + cell id)
     uint32_t *vals[2];    // [N] concatenated element index
     uint32_t *hist;       // [256 * nblk] digit-major block histograms
-    uint32_t *cellcnt;    // [C + 1] concatenated cell counts -> cell starts
+    uint32_t *cellcnt;    // [C + 1] first sorted slot of each concatenated cell key
 };
 
 // Cell of one coordinate, exactly as the method defines it: s = x * kappa
