@@ -115,7 +115,9 @@ __global__ void __launch_bounds__(256) k_accel_simple(const DevBox *boxes) {
     }
 }
 
-// Gather the caller-order cotangent into sorted order (float4 per slot).
+// VJP source records in sorted order, two float4 per slot: the slot's offset
+// (ox, oy, oz, cz) and its caller-order cotangent gathered to it (vx, vy, vz, 0),
+// so that a source is one 32-byte record.
 __global__ void __launch_bounds__(256) k_gather_cot(const DevBox *boxes, float4 *cot_sorted) {
     const DevBox &B = boxes[blockIdx.y];
     const int s = blockIdx.x * 256 + threadIdx.x;
@@ -123,7 +125,8 @@ __global__ void __launch_bounds__(256) k_gather_cot(const DevBox *boxes, float4 
     const int i = B.order[s];
     if (i < 0 || i >= B.n) return;
     const float *v = B.cot + 3 * (int64_t)i;
-    cot_sorted[B.base + s] = make_float4(v[0], v[1], v[2], 0.0f);
+    cot_sorted[2 * (B.base + s)] = B.off[s];
+    cot_sorted[2 * (B.base + s) + 1] = make_float4(v[0], v[1], v[2], 0.0f);
 }
 
 // VJP per pair: with r = x_j - x_i (cell widths), g = F/r and h = g'(rho)/rho,
@@ -139,11 +142,11 @@ __global__ void __launch_bounds__(256) k_vjp_simple(const DevBox *boxes,
     const int K = B.K;
     const int32_t *__restrict__ cs = B.cell_start;
     const float4 *__restrict__ off = B.off;
-    const float4 *__restrict__ cv = cot_sorted + B.base;
+    const float4 *__restrict__ cv = cot_sorted + 2 * B.base;   // records: offset, cotangent
     const int c = find_cell(cs, B.ncell, s);
     const int cz = c % K, cy = (c / K) % K, cx = c / (K * K);
     const float4 oi = off[s];
-    const float4 vi = cv[s];
+    const float4 vi = cv[2 * s + 1];
     const float cA = B.cA, cB = B.cB, cC2 = 2.0f * B.cC, cC = B.cC;
     const float eps2 = B.eps * B.eps;
     const bool fast = B.outer_newton != 0;
@@ -165,7 +168,7 @@ __global__ void __launch_bounds__(256) k_vjp_simple(const DevBox *boxes,
                                                         dy == 2 || dz == -2 || dz == 2));
                 for (int j = j0; j < j1; ++j) {
                     const float4 oj = off[j];
-                    const float4 vj = cv[j];
+                    const float4 vj = cv[2 * j + 1];
                     const float rx = oj.x - sx, ry = oj.y - sy, rz = oj.z - sz;
                     const float ux = vj.x - vi.x, uy = vj.y - vi.y, uz = vj.z - vi.z;
                     float r2 = __builtin_fmaf(rx, rx, floor2);

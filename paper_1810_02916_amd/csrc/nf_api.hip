@@ -162,8 +162,8 @@ int validate(int nbox, const nf_box *boxes, Layout &L) {
     const size_t bin_end = o;
     // force scratch reuses the binning scratch region
     o = scratch0;
-    L.cot_off = o;
-    o = align_up(o + 16 * (size_t)L.N, 256);
+    L.cot_off = o;   // VJP source records: 32 bytes per particle
+    o = align_up(o + 32 * (size_t)L.N, 256);
     L.cellinfo_off = o;
     o = align_up(o + 4 * (size_t)L.C, 256);
     L.bucket_off = o;

@@ -83,7 +83,7 @@ struct ForcePlan {
     int64_t max_n = 0;
     bool compensated = false;
     bool simple = false;
-    float4 *cot_sorted = nullptr;   // vjp only: [N] cotangents in sorted order
+    float4 *cot_sorted = nullptr;   // vjp only: [2N] source records (offset, cotangent), sorted
     int64_t N = 0;
 };
 

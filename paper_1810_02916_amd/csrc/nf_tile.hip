@@ -289,6 +289,8 @@ __device__ __forceinline__ void store(const DevBox &B, int slot, float3 f) {
 // ------------------------------------------------------------------ dense path
 
 typedef const __attribute__((address_space(4))) float cfloat;
+typedef float rec8 __attribute__((ext_vector_type(8)));
+typedef const __attribute__((address_space(4))) rec8 crec8;
 typedef const __attribute__((address_space(1))) float gfloat;
 
 // A float4 of a global array through a global-address-space pointer (plain
@@ -317,8 +319,10 @@ __device__ __forceinline__ void run_scalar(cfloat *__restrict__ src, cfloat *__r
                 pair_accel<SPLINE>(src[4 * j], src[4 * j + 1], src[4 * j + 2], xs, ys, zs, k, px,
                                    py, pz);
             } else {
-                pair_vjp<SPLINE>(src[4 * j], src[4 * j + 1], src[4 * j + 2], cot[4 * j],
-                                 cot[4 * j + 1], cot[4 * j + 2], xs, ys, zs, vi.x, vi.y, vi.z, k,
+                // one 32-byte record per source (offset, cotangent), one scalar load
+                const rec8 r8 = ((crec8 *)src)[j];
+                pair_vjp<SPLINE>(r8[0], r8[1], r8[2], r8[4], r8[5], r8[6], xs, ys, zs, vi.x,
+                                 vi.y, vi.z, k,
                                  px, py, pz);
             }
         }
@@ -360,12 +364,14 @@ k_dense(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
         const int slot = s0 + (active ? lane : 0);
         const float4 oi = B.off[slot];
         float4 vi = make_float4(0.f, 0.f, 0.f, 0.f);
-        if constexpr (MODE == 1) vi = cot_sorted[B.base + slot];
+        if constexpr (MODE == 1) vi = cot_sorted[2 * (B.base + slot) + 1];
         const Coef k{B.cA, B.cB, B.cC, 2.0f * B.cC, B.eps * B.eps, B.r2floor};
         const bool fast = B.outer_newton != 0;
         const bool plummer = B.plummer != 0;   // Plummer law: one branch for every pair
         cfloat *src = (cfloat *)B.off;
-        cfloat *cot = (cfloat *)(cot_sorted + B.base);
+        // the VJP reads sources from the 32-byte records (offset, cotangent)
+        cfloat *cot = (cfloat *)(cot_sorted + 2 * B.base);
+        if constexpr (MODE == 1) src = cot;
         // cell ranges of the 125 source cells: lane r < 25 holds row r's five
         // (start, end) pairs, read back with readlane (uniform, no memory wait)
         int cb[5], ce[5];
@@ -533,7 +539,7 @@ k_light(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
         const int b = active ? lane / g : 0;
         const float4 oi = off[s0 + a];
         float4 vi = make_float4(0.f, 0.f, 0.f, 0.f);
-        if constexpr (MODE == 1) vi = cot_sorted[B.base + s0 + a];
+        if constexpr (MODE == 1) vi = cot_sorted[2 * (B.base + s0 + a) + 1];
 
         // ---- pieces and run table: wave 0, one lane per row.  Staged layout: the
         //      inner parts of rows 0..24, then their outer parts; the non-empty
@@ -668,8 +674,12 @@ k_light(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
                 if (d[i] < u1) {
                     const float4 dsc = sm.rd[pos[i]];
                     const int gsrc = d[i] + __float_as_int(dsc.x);
-                    buf[i] = ld_global4(goff, gsrc);
-                    if constexpr (MODE == 1) cb[i] = ld_global4(gcot, B.base + gsrc);
+                    if constexpr (MODE == 1) {   // the source's 32-byte record
+                        buf[i] = ld_global4(gcot, 2 * (B.base + gsrc));
+                        cb[i] = ld_global4(gcot, 2 * (B.base + gsrc) + 1);
+                    } else {
+                        buf[i] = ld_global4(goff, gsrc);
+                    }
                     sh[i][0] = dsc.y;
                     sh[i][1] = dsc.z;
                     sh[i][2] = dsc.w;
