@@ -223,7 +223,8 @@ def main():
     b, a_plain, a_comp, g = out
 
     # The widened rows, timed after the step (not part of value): the Plummer
-    # law (plain accelerations) and the p = 8 cell multipoles.
+    # law (plain accelerations), the p = 8 cell multipoles, the time-step
+    # statistics and the kick/drift update.
     def timed(fn, reps=args.steps):
         fn()
         e0 = torch.cuda.Event(enable_timing=True)
@@ -237,6 +238,13 @@ def main():
         return e0.elapsed_time(e1) / reps
     t_plum = timed(lambda: nfp.accel(b, 1.0, plummer=True))
     t_mom = timed(lambda: nfp.multipoles(b, 8))
+    vel = torch.randn((sp.n, 3), generator=torch.Generator(device=dev).manual_seed(sp.seed * 10 + 3),
+                      device=dev, dtype=torch.float32)
+    t_stats = timed(lambda: nfp.step_stats(b, a_plain, vel))
+    pos2, vel2 = pos.clone(), vel.clone()
+    t_kd = timed(lambda: nfp.kick_drift(b, a_plain, vel2, pos2, 1e-6, 1e-6))
+    stats_bytes = 28.0 * sp.n + 4.0 * (sp.K ** 3 + 1) + 8.0 * sp.K ** 3 + 24.0 * sp.K ** 3
+    kd_bytes = 84.0 * sp.n
     mom_bytes = 16.0 * sp.n + 4.0 * nfp.multipole_terms(8) * sp.K ** 3 + 4.0 * (sp.K ** 3 + 1)
     extras = {
         "plummer_accel_plain": {"ms": round(t_plum, 4), "gdips": round(I / t_plum / 1e6, 2)},
@@ -244,6 +252,11 @@ def main():
                           "algorithmic_bytes": int(mom_bytes),
                           "hbm_gbs": round(mom_bytes / (t_mom * 1e-3) / 1e9, 1),
                           "hbm_frac": round(mom_bytes / (t_mom * 1e-3) / PEAK_HBM, 4)},
+        "step_stats": {"ms": round(t_stats, 4), "algorithmic_bytes": int(stats_bytes),
+                       "hbm_gbs": round(stats_bytes / (t_stats * 1e-3) / 1e9, 1)},
+        "kick_drift": {"ms": round(t_kd, 4), "algorithmic_bytes": int(kd_bytes),
+                       "hbm_gbs": round(kd_bytes / (t_kd * 1e-3) / 1e9, 1),
+                       "hbm_frac": round(kd_bytes / (t_kd * 1e-3) / PEAK_HBM, 4)},
     }
     result = {
         "metric": "G pair-interactions/s and particles/s (FP32 vs compensated, err vs FP64)",
