@@ -38,7 +38,7 @@ struct TilePlan {
     uint32_t *bucket_off = nullptr;   // [plan_buckets()] first item of each bucket
     uint32_t *totals = nullptr;  // [2] dense and light item counts
     Item *dense = nullptr;       // dense items, heaviest first
-    Item *light = nullptr;       // light items, heaviest first
+    Item *light = nullptr;       // light items, in spatial slabs
     uint32_t *counter = nullptr; // [queue_words()] queue counters
 };
 int plan_buckets();

@@ -65,8 +65,9 @@ __device__ int block_sources(const int32_t *cs, int K, int cx, int cy, int cz) {
     return s;
 }
 
-// Cost buckets: quarter octaves of a pair count.  A dense item (64 sinks)
-// costs in proportion to its block's source count S, a light item to g * S.
+// Buckets, placed highest first: dense items by cost (quarter octaves of
+// their block's source count S, heaviest first); light items by spatial slab
+// (128 slabs of consecutive cells, in cell order).
 constexpr int kBuckets = 128;
 constexpr int kKinds = 2;                  // 0: dense, 1: light
 __device__ __forceinline__ int cost_bucket(float pairs) {
@@ -108,7 +109,10 @@ k_plan_count(const DevBox *boxes, uint32_t *cellinfo, uint32_t *bucket_cnt) {
                 info |= (uint32_t)(b + 1);
             }
             if (it.light) {
-                const int b = cost_bucket((float)(n % kUnit) * S);
+                // light items run in spatial order (slabs of consecutive cells):
+                // neighbouring items share their staged sources in L2, and the
+                // dense kernel, running alongside, absorbs the tail
+                const int b = kBuckets - 1 - (int)((int64_t)c * kBuckets / B.ncell);
                 atomicAdd(&h[kBuckets + b], 1u);
                 info |= (uint32_t)(b + 1) << 16;
             }
