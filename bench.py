@@ -237,6 +237,7 @@ def main():
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps
     t_plum = timed(lambda: nfp.accel(b, 1.0, plummer=True))
+    t_full = timed(lambda: nfp.accel(b, 1.0, spline_everywhere=True))
     t_mom = timed(lambda: nfp.multipoles(b, 8))
     vel = torch.randn((sp.n, 3), generator=torch.Generator(device=dev).manual_seed(sp.seed * 10 + 3),
                       device=dev, dtype=torch.float32)
@@ -248,6 +249,7 @@ def main():
     mom_bytes = 16.0 * sp.n + 4.0 * nfp.multipole_terms(8) * sp.K ** 3 + 4.0 * (sp.K ** 3 + 1)
     extras = {
         "plummer_accel_plain": {"ms": round(t_plum, 4), "gdips": round(I / t_plum / 1e6, 2)},
+        "accel_plain_shortcut_off": {"ms": round(t_full, 4), "gdips": round(I / t_full / 1e6, 2)},
         "multipoles_p8": {"ms": round(t_mom, 4), "terms": nfp.multipole_terms(8),
                           "algorithmic_bytes": int(mom_bytes),
                           "hbm_gbs": round(mom_bytes / (t_mom * 1e-3) / 1e9, 1),

@@ -79,7 +79,14 @@ enum {
     /* Plummer softening instead of Eq. 2 (Sec. 4.3, the Plummer law):
        F(r) = r / (r^2 + eps_p^2)^(3/2) for every pair of the block, with the
        box's eps_s field read as the Plummer length eps_p. */
-    NF_PLUMMER = 1u << 2
+    NF_PLUMMER = 1u << 2,
+    /* Evaluate Eq. 2's min form for every pair: the outer-shell shortcut (a
+       cell with some |d| = 2 is at r >= 1 cell, so for eps_s <= 1 cell the
+       min always selects r^-3 there) is switched off.  Every pair takes the
+       same branch as before, so results differ only in the FP32 summation
+       order (the light kernel then slices one segment instead of two); the
+       point is the cost (for measurement). */
+    NF_SPLINE_EVERYWHERE = 1u << 3
 };
 
 /* Upper bound on boxes per call. */

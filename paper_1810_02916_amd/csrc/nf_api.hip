@@ -213,7 +213,8 @@ int check_ws(const Layout &L, void *ws, size_t ws_bytes) {
     return NF_OK;
 }
 
-void fill_geometry(const nf_box &B, const Layout &L, int b, DevBox &d, bool plummer = false) {
+void fill_geometry(const nf_box &B, const Layout &L, int b, DevBox &d, bool plummer = false,
+                   bool no_shortcut = false) {
     std::memset(&d, 0, sizeof d);
     d.n = (int32_t)B.n;
     d.K = B.K;
@@ -226,7 +227,7 @@ void fill_geometry(const nf_box &B, const Layout &L, int b, DevBox &d, bool plum
     d.cA = (float)(10.0 / (eps * eps * eps));
     d.cB = (float)(-15.0 / (eps * eps * eps * eps));
     d.cC = (float)(6.0 / (eps * eps * eps * eps * eps));
-    d.outer_newton = eps <= 1.0 ? 1 : 0;
+    d.outer_newton = (eps <= 1.0 && !no_shortcut) ? 1 : 0;
     d.plummer = plummer ? 1 : 0;
     d.r2floor = plummer ? (float)(eps * eps) : kR2Floor;
     d.dense_min = B.dense_min ? B.dense_min : kDefaultDenseMin;
@@ -319,7 +320,7 @@ static int force_common(int nbox, const nf_box *boxes, double gm, uint32_t flags
     int rc = validate(nbox, boxes, L);
     if (rc) return rc;
     if (!std::isfinite(gm)) return fail(NF_EINVAL, "gm must be finite");
-    if (flags & ~(uint32_t)(NF_COMPENSATED | NF_SIMPLE | NF_PLUMMER))
+    if (flags & ~(uint32_t)(NF_COMPENSATED | NF_SIMPLE | NF_PLUMMER | NF_SPLINE_EVERYWHERE))
         return fail(NF_EINVAL, "unknown flag bits");
     if (!out) return fail(NF_EINVAL, "output pointer array is NULL");
     if (vjp && !cot) return fail(NF_EINVAL, "cotangent pointer array is NULL");
@@ -332,7 +333,8 @@ static int force_common(int nbox, const nf_box *boxes, double gm, uint32_t flags
     if ((rc = check_device(why))) return fail(rc, why);
     std::vector<DevBox> tab((size_t)nbox);
     for (int b = 0; b < nbox; ++b) {
-        fill_geometry(boxes[b], L, b, tab[b], (flags & NF_PLUMMER) != 0);
+        fill_geometry(boxes[b], L, b, tab[b], (flags & NF_PLUMMER) != 0,
+                      (flags & NF_SPLINE_EVERYWHERE) != 0);
         const double k = tab[b].kappa;
         tab[b].scale = (float)(vjp ? gm * k * k * k : gm * k * k);
         tab[b].out = out[b];

@@ -18,7 +18,7 @@ from typing import List, Optional, Sequence
 import torch
 
 from . import _lib
-from ._lib import NF_COMPENSATED, NF_PLUMMER, NF_SIMPLE, NfBox
+from ._lib import NF_COMPENSATED, NF_PLUMMER, NF_SIMPLE, NF_SPLINE_EVERYWHERE, NfBox
 
 __all__ = [
     "SPLINE_PER_PLUMMER",
@@ -180,9 +180,11 @@ def bin_particles(pos: torch.Tensor, K: int, L: float, eps_s: float,
     return bin_particles_batched([pos], [K], [L], [eps_s], dense_min)
 
 
-def _flags(compensated: bool, simple: bool, plummer: bool = False) -> int:
+def _flags(compensated: bool, simple: bool, plummer: bool = False,
+           spline_everywhere: bool = False) -> int:
     return ((NF_COMPENSATED if compensated else 0) | (NF_SIMPLE if simple else 0)
-            | (NF_PLUMMER if plummer else 0))
+            | (NF_PLUMMER if plummer else 0)
+            | (NF_SPLINE_EVERYWHERE if spline_everywhere else 0))
 
 
 def _ptr_array(tensors: Sequence[torch.Tensor]):
@@ -193,16 +195,19 @@ def _ptr_array(tensors: Sequence[torch.Tensor]):
 
 
 def accel(b: Binned, gm: float = 1.0, *, compensated: bool = False, simple: bool = False,
-          plummer: bool = False, out: Optional[List[torch.Tensor]] = None):
+          plummer: bool = False, spline_everywhere: bool = False,
+          out: Optional[List[torch.Tensor]] = None):
     """Near-field accelerations, float32 [n,3] in input order (a list for
     several boxes).  ``plummer``: the Plummer law of Sec. 4.3 with each box's
-    softening length read as eps_p, instead of Eq. 2."""
+    softening length read as eps_p, instead of Eq. 2.  ``spline_everywhere``:
+    the outer-shell shortcut off (same results, for measurement)."""
     lib = _lib.load()
     if out is None:
         out = [torch.empty((bx.n, 3), dtype=torch.float32, device=b.device) for bx in b.boxes]
     ptrs = _ptr_array(out)
     with torch.cuda.device(b.device):
-        rc = lib.nf_accel(b.nbox, b.carray(), float(gm), _flags(compensated, simple, plummer), ptrs,
+        rc = lib.nf_accel(b.nbox, b.carray(), float(gm),
+                          _flags(compensated, simple, plummer, spline_everywhere), ptrs,
                           ctypes.c_void_p(b.workspace.data_ptr()), b.workspace.numel(),
                           _stream_handle(b.device))
     _lib.check(rc)

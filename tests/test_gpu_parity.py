@@ -320,6 +320,21 @@ def test_plummer_large_softening_and_autograd():
     assert err_stats(p.grad.cpu().numpy(), refg)["rms"] <= TOL_PLAIN
 
 
+def test_spline_everywhere_matches_the_shortcut():
+    """The outer-shell shortcut takes the branch the min form would take, so
+    switching it off changes only the FP32 summation order (and the cost);
+    both agree with the oracle."""
+    sp = WORKLOADS["clustered262k"]
+    pos = make_box(sp)
+    b = nfp.bin_particles(_gpu(pos), sp.K, sp.L, sp.eps_s)
+    ref = oracle.accel(pos, sp.K, sp.L, sp.eps_s)
+    for comp in (False, True):
+        a = nfp.accel(b, 1.0, compensated=comp).cpu().numpy().astype(np.float64)
+        f = nfp.accel(b, 1.0, compensated=comp, spline_everywhere=True).cpu().numpy()
+        assert err_stats(f.astype(np.float64), a)["rms"] <= (1e-7 if comp else 2e-6)
+        assert err_stats(f.astype(np.float64), ref)["rms"] <= (TOL_COMP if comp else TOL_PLAIN)
+
+
 def test_tile_large_softening_uses_spline_everywhere():
     """eps above one cell width: the outer-shell Newton shortcut must be off."""
     K, L = 8, 1.0
