@@ -36,9 +36,9 @@ struct TilePlan {
     uint32_t *cellinfo = nullptr;     // [TG] item kind and cost bucket per cell
     uint32_t *bucket_cnt = nullptr;   // [plan_buckets()] items per (kind, cost bucket)
     uint32_t *bucket_off = nullptr;   // [plan_buckets()] first item of each bucket
-    uint32_t *totals = nullptr;  // [2] dense and light item counts
+    uint32_t *totals = nullptr;  // [3] dense, light and narrow item counts
     Item *dense = nullptr;       // dense items, heaviest first
-    Item *light = nullptr;       // light items, in spatial slabs
+    Item *light = nullptr;       // light items, then narrow items, each in spatial slabs
     uint32_t *counter = nullptr; // [queue_words()] queue counters
 };
 int plan_buckets();

@@ -20,6 +20,10 @@
 //               segments; the g sinks are spread over the 256 threads as
 //               (sink a, source slice b), thread = a + g b, P = 256 / g
 //               slices, summed at the end by a fixed-order pairwise tree.
+//   * narrow -- a light item of fewer than kNarrow sinks: the same kernel on
+//               one wave per workgroup (P = 64 / g), so the per-item costs
+//               that do not shrink with g (item setup, the per-wave header,
+//               the slice tree) are paid by one wave instead of four.
 // In both paths a source of the sink's own cell is used unshifted, so the
 // closest pairs are formed from the exact float offsets, and a cell of the
 // outer shell of the block (some |d| = 2) is at r >= 1 and takes the Newton
@@ -41,6 +45,8 @@ constexpr int kQueues = 32;          // light-item queues (a multiple of the 8 X
 constexpr int kQueueStride = 32;     // words between queue counters (own 128-byte line)
 constexpr int kLightWaves = 4;       // waves sharing one light item
 constexpr int kLightThreads = 64 * kLightWaves;
+constexpr int kNarrowThreads = 64;   // one wave per narrow item
+constexpr int kNarrow = 12;          // light items of fewer sinks are narrow
 constexpr int kRows = 25;            // (dx, dy) rows of the 5x5x5 block
 constexpr int kFlush = 32;           // compensated mode: plain partials of <= 32 terms
 
@@ -66,10 +72,10 @@ __device__ int block_sources(const int32_t *cs, int K, int cx, int cy, int cz) {
 }
 
 // Buckets, placed highest first: dense items by cost (quarter octaves of
-// their block's source count S, heaviest first); light items by spatial slab
-// (128 slabs of consecutive cells, in cell order).
+// their block's source count S, heaviest first); light and narrow items by
+// spatial slab (128 slabs of consecutive cells, in cell order).
 constexpr int kBuckets = 128;
-constexpr int kKinds = 2;                  // 0: dense, 1: light
+constexpr int kKinds = 3;                  // 0: dense, 1: light, 2: narrow
 __device__ __forceinline__ int cost_bucket(float pairs) {
     const float l = __log2f(fmaxf(pairs, 1.0f));
     return min(kBuckets - 1, (int)(4.0f * l));
@@ -77,16 +83,18 @@ __device__ __forceinline__ int cost_bucket(float pairs) {
 
 // Items of a cell of n particles: n / 64 full dense chunks, and the last
 // n % 64 sinks as one more dense chunk if they are at least dense_min, else as
-// one light item.  cellinfo packs (dense bucket + 1) | (light bucket + 1) << 16,
-// 0 for none; the item counts per (kind, bucket) are summed in LDS first so
-// that each block adds one value per non-empty bucket.
+// one light item (a narrow one below kNarrow sinks).  cellinfo packs
+// (dense bucket + 1) | (light bucket + 1) << 16, 0 for none; the item counts
+// per (kind, bucket) are summed in LDS first so that each block adds one value
+// per non-empty bucket.
 struct CellItems {
     int ndense;     // dense chunks
-    bool light;     // one light item for the remainder
+    int light;      // kind of the remainder's item: 0 none, 1 light, 2 narrow
 };
 __device__ __forceinline__ CellItems cell_items(int n, int dense_min) {
     const int full = n / kUnit, rem = n % kUnit;
-    return CellItems{full + (rem >= dense_min ? 1 : 0), rem > 0 && rem < dense_min};
+    const int lk = (rem > 0 && rem < dense_min) ? (rem < kNarrow ? 2 : 1) : 0;
+    return CellItems{full + (rem >= dense_min ? 1 : 0), lk};
 }
 
 __global__ void __launch_bounds__(256)
@@ -113,7 +121,7 @@ k_plan_count(const DevBox *boxes, uint32_t *cellinfo, uint32_t *bucket_cnt) {
                 // neighbouring items share their staged sources in L2, and the
                 // dense kernel, running alongside, absorbs the tail
                 const int b = kBuckets - 1 - (int)((int64_t)c * kBuckets / B.ncell);
-                atomicAdd(&h[kBuckets + b], 1u);
+                atomicAdd(&h[it.light * kBuckets + b], 1u);
                 info |= (uint32_t)(b + 1) << 16;
             }
         }
@@ -141,11 +149,12 @@ k_plan_buckets(uint32_t *bucket_cnt, uint32_t *bucket_off, uint32_t *totals) {
 
 // Items into their bucket ranges: each block reserves one range per non-empty
 // bucket with a global atomic and places its cells by LDS ranks.  The order
-// inside a bucket depends on timing; every item's result does not.
+// inside a bucket depends on timing; every item's result does not.  Narrow
+// items follow the light ones in the same array.
 __global__ void __launch_bounds__(256)
 k_plan_emit(const DevBox *boxes, const uint32_t *__restrict__ cellinfo,
-            const uint32_t *__restrict__ bucket_off, uint32_t *bucket_cur, Item *dense,
-            Item *light) {
+            const uint32_t *__restrict__ bucket_off, const uint32_t *__restrict__ totals,
+            uint32_t *bucket_cur, Item *dense, Item *light) {
     __shared__ uint32_t h[kKinds * kBuckets];
     __shared__ uint32_t base[kKinds * kBuckets];
     for (int t = threadIdx.x; t < kKinds * kBuckets; t += 256) h[t] = 0;
@@ -154,7 +163,7 @@ k_plan_emit(const DevBox *boxes, const uint32_t *__restrict__ cellinfo,
     const int c = blockIdx.x * 256 + threadIdx.x;
     uint32_t info = 0, rd = 0, rl = 0;
     int n = 0, bd = 0, bl = 0;
-    CellItems it{0, false};
+    CellItems it{0, 0};
     if (c < B.ncell) {
         info = cellinfo[B.cellbase + c];
         if (info) {
@@ -163,7 +172,7 @@ k_plan_emit(const DevBox *boxes, const uint32_t *__restrict__ cellinfo,
             bd = (int)(info & 0xffffu) - 1;
             bl = (int)(info >> 16) - 1;
             if (it.ndense) rd = atomicAdd(&h[bd], (uint32_t)it.ndense);
-            if (it.light) rl = atomicAdd(&h[kBuckets + bl], 1u);
+            if (it.light) rl = atomicAdd(&h[it.light * kBuckets + bl], 1u);
         }
     }
     __syncthreads();
@@ -174,7 +183,10 @@ k_plan_emit(const DevBox *boxes, const uint32_t *__restrict__ cellinfo,
         const uint32_t at = base[bd] + rd;
         for (int k = 0; k < it.ndense; ++k) dense[at + k] = Item{(int)blockIdx.y, c, 1, k};
     }
-    if (it.light) light[base[kBuckets + bl] + rl] = Item{(int)blockIdx.y, c, 1, n / kUnit};
+    if (it.light) {
+        const uint32_t at = (it.light == 2 ? totals[1] : 0u) + base[it.light * kBuckets + bl] + rl;
+        light[at] = Item{(int)blockIdx.y, c, 1, n / kUnit};
+    }
 }
 
 // ------------------------------------------------------------------ pair arithmetic
@@ -422,11 +434,11 @@ k_dense(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
 constexpr int kSlots = 4;
 constexpr int kPiece = kRows * kSlots;
 
-template <int MODE, int CAP>
+template <int MODE, int CAP, int NT>
 struct LightSmem {
     union {
         float4 sx[CAP];                  // (o_x + dx, o_y + dy, o_z + dz, v_x)
-        float red[6][kLightThreads];     // after the sum: slice partials (sum, compensation)
+        float red[6][NT];                // after the sum: slice partials (sum, compensation)
     };
     float2 sv[MODE == 1 ? CAP : 1];  // (v_y, v_z) for the VJP
     int rs[128];                     // staged start of each non-empty piece (run), ascending,
@@ -491,15 +503,20 @@ __device__ __forceinline__ void segment(const float4 *__restrict__ sx, const flo
     }
 }
 
-template <int MODE, bool COMP, int CAP>
-__global__ void __launch_bounds__(kLightThreads) __attribute__((amdgpu_waves_per_eu(MODE == 0 ? 8 : 7)))
-k_light(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
+// NT threads share one item (256 for light items, 64 for narrow ones); cls
+// selects the item class: 1 light (items from the start of the array), 2
+// narrow (after the light ones).
+template <int MODE, bool COMP, int CAP, int NT>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MODE == 0 ? 8 : 7)))
+k_light(const DevBox *__restrict__ boxes, const Item *__restrict__ all_items,
         const uint32_t *__restrict__ totals, uint32_t *counter,
-        const float4 *__restrict__ cot_sorted) {
-    static_assert(CAP % kLightThreads == 0, "a staging window is whole rounds of the workgroup");
-    __shared__ LightSmem<MODE, CAP> sm;
-    const int lane = threadIdx.x;   // 0 .. kLightThreads-1, all waves share the item
-    const int nitems = (int)totals[1];
+        const float4 *__restrict__ cot_sorted, int cls) {
+    static_assert(CAP % NT == 0, "a staging window is whole rounds of the workgroup");
+    static_assert(NT % 64 == 0 && NT <= kLightThreads, "whole waves");
+    __shared__ LightSmem<MODE, CAP, NT> sm;
+    const int lane = threadIdx.x;   // 0 .. NT-1, all waves share the item
+    const int nitems = (int)totals[cls];
+    const Item *__restrict__ items = all_items + (cls == 2 ? totals[1] : 0u);
 
     // kQueues interleaved queues: workgroup w draws from queue q = w % kQueues,
     // whose k-th claim is item k * kQueues + q.  A single counter would cap
@@ -537,7 +554,7 @@ k_light(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
         // ---- this lane's sink (sink a, source slice b), loaded before the setup
         const Coef k{B.cA, B.cB, B.cC, 2.0f * B.cC, B.eps * B.eps, B.r2floor};
         const bool fast = B.outer_newton != 0;
-        const int P = kLightThreads / g;
+        const int P = NT / g;
         const bool active = lane < g * P;
         const int a = active ? lane % g : 0;
         const int b = active ? lane / g : 0;
@@ -651,17 +668,17 @@ k_light(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
         const int inner = uni(sm.inner);
         const bool single = total <= CAP;
 
-        // stage the union window [u0, u1): thread t takes elements u0 + t + 256 i,
+        // stage the union window [u0, u1): thread t takes elements u0 + t + NT i,
         // finds their runs by a branch-free 7-step binary search over the run
         // starts (padded with INT_MAX), the searches of its elements interleaved,
         // and issues all its loads before any LDS store
         auto stage = [&](int u0, int u1) {
-            constexpr int kPer = CAP / kLightThreads;
+            constexpr int kPer = CAP / NT;
             int pos[kPer], d[kPer];
 #pragma unroll
             for (int i = 0; i < kPer; ++i) {
                 pos[i] = 0;
-                d[i] = u0 + lane + kLightThreads * i;
+                d[i] = u0 + lane + NT * i;
             }
 #pragma unroll
             for (int st = 64; st > 0; st >>= 1) {
@@ -794,16 +811,17 @@ int persistent_grid(Kern kern, int threads) {
     return std::max(1, ncu) * std::max(1, per);
 }
 
-// The dense and light kernels of one call run concurrently: the light kernel
-// goes to a library stream of the same device (default priority), forked from
-// and joined back to the caller's stream with events, so the two kernels
-// share the CUs (the dense kernel uses no LDS, the light kernel little VALU
-// latency hiding of its own) and neither's tail is exposed.  Under graph
-// capture the fork and join become graph dependencies.  The sequence is
-// enqueued under a lock: the events are shared by all calls on the device.
+// The dense, light and narrow kernels of one call run concurrently: the
+// light and narrow kernels go to two library streams of the same device
+// (default priority), forked from and joined back to the caller's stream with
+// events, so the kernels share the CUs (the dense kernel uses no LDS and
+// waits on scalar loads, the light kernels lean on LDS) and no kernel's tail
+// runs alone.  Under graph capture the fork and joins become graph
+// dependencies.  The sequence is enqueued under a lock: the events are shared
+// by all calls on the device.
 struct SideStream {
-    hipStream_t s = nullptr;
-    hipEvent_t fork = nullptr, join = nullptr;
+    hipStream_t s[2] = {nullptr, nullptr};
+    hipEvent_t fork = nullptr, join[2] = {nullptr, nullptr};
 };
 std::mutex g_side_mu;
 std::vector<SideStream> g_side;
@@ -814,10 +832,18 @@ hipError_t side_stream(SideStream &out) {   // caller holds g_side_mu
     if (e != hipSuccess) return e;
     if ((int)g_side.size() <= dev) g_side.resize(dev + 1);
     SideStream &ss = g_side[dev];
-    if (!ss.s) {
-        if ((e = hipStreamCreateWithFlags(&ss.s, hipStreamNonBlocking)) != hipSuccess) return e;
-        if ((e = hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming)) != hipSuccess) return e;
-        if ((e = hipEventCreateWithFlags(&ss.join, hipEventDisableTiming)) != hipSuccess) return e;
+    if (!ss.join[1]) {   // created in this order, so the last one marks completion
+        if (!ss.fork &&
+            (e = hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming)) != hipSuccess)
+            return e;
+        for (int k = 0; k < 2; ++k) {
+            if (!ss.s[k] &&
+                (e = hipStreamCreateWithFlags(&ss.s[k], hipStreamNonBlocking)) != hipSuccess)
+                return e;
+            if (!ss.join[k] &&
+                (e = hipEventCreateWithFlags(&ss.join[k], hipEventDisableTiming)) != hipSuccess)
+                return e;
+        }
     }
     out = ss;
     return hipSuccess;
@@ -827,32 +853,45 @@ template <int MODE, bool COMP>
 hipError_t launch_force(const DevBox *d_boxes, const TilePlan &tp, const float4 *cot,
                         hipStream_t s) {
     constexpr int CAP = MODE == 0 ? 1024 : 768;
+    constexpr int NCAP = MODE == 0 ? 256 : 192;   // narrow items: 4.5 KB windows
     static const int gd = persistent_grid(k_dense<MODE, COMP>, kUnit);
-    // every queue needs at least one workgroup: the grid is a multiple of kQueues
+    // every queue needs at least one workgroup: the grids are multiples of kQueues
     static const int gl =
-        (persistent_grid(k_light<MODE, COMP, CAP>, kLightThreads) + kQueues - 1) / kQueues *
-        kQueues;
+        (persistent_grid(k_light<MODE, COMP, CAP, kLightThreads>, kLightThreads) + kQueues - 1) /
+        kQueues * kQueues;
+    static const int gn =
+        (persistent_grid(k_light<MODE, COMP, NCAP, kNarrowThreads>, kNarrowThreads) + kQueues -
+         1) / kQueues * kQueues;
     std::lock_guard<std::mutex> lk(g_side_mu);
     SideStream ss;
     hipError_t e = side_stream(ss);
     if (e != hipSuccess) return e;
     if ((e = hipEventRecord(ss.fork, s)) != hipSuccess) return e;
-    if ((e = hipStreamWaitEvent(ss.s, ss.fork, 0)) != hipSuccess) return e;
-    hipLaunchKernelGGL((k_light<MODE, COMP, CAP>), dim3(gl), dim3(kLightThreads), 0, ss.s,
-                       d_boxes, (const Item *)tp.light, (const uint32_t *)tp.totals,
-                       tp.counter + kQueueStride, cot);
+    for (int k = 0; k < 2; ++k)
+        if ((e = hipStreamWaitEvent(ss.s[k], ss.fork, 0)) != hipSuccess) return e;
+    hipLaunchKernelGGL((k_light<MODE, COMP, CAP, kLightThreads>), dim3(gl), dim3(kLightThreads),
+                       0, ss.s[0], d_boxes, (const Item *)tp.light, (const uint32_t *)tp.totals,
+                       tp.counter + kQueueStride, cot, 1);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = hipEventRecord(ss.join, ss.s)) != hipSuccess) return e;
+    if ((e = hipEventRecord(ss.join[0], ss.s[0])) != hipSuccess) return e;
+    hipLaunchKernelGGL((k_light<MODE, COMP, NCAP, kNarrowThreads>), dim3(gn),
+                       dim3(kNarrowThreads), 0, ss.s[1], d_boxes, (const Item *)tp.light,
+                       (const uint32_t *)tp.totals, tp.counter + kQueueStride * (1 + kQueues), cot,
+                       2);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = hipEventRecord(ss.join[1], ss.s[1])) != hipSuccess) return e;
     hipLaunchKernelGGL((k_dense<MODE, COMP>), dim3(gd), dim3(kUnit), 0, s, d_boxes,
                        (const Item *)tp.dense, (const uint32_t *)tp.totals, tp.counter, cot);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    return hipStreamWaitEvent(s, ss.join, 0);
+    for (int k = 0; k < 2; ++k)
+        if ((e = hipStreamWaitEvent(s, ss.join[k], 0)) != hipSuccess) return e;
+    return hipSuccess;
 }
 
 }  // namespace
 
 int plan_buckets() { return kKinds * kBuckets; }
-int queue_words() { return (1 + kQueues) * kQueueStride; }
+int queue_words() { return (1 + 2 * kQueues) * kQueueStride; }
 
 hipError_t plan_launch(const DevBox *d_boxes, int nbox, const TilePlan &tp, hipStream_t s) {
     hipError_t e;
@@ -865,7 +904,7 @@ hipError_t plan_launch(const DevBox *d_boxes, int nbox, const TilePlan &tp, hipS
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_plan_emit, grid, dim3(256), 0, s, d_boxes,
                        (const uint32_t *)tp.cellinfo, (const uint32_t *)tp.bucket_off,
-                       tp.bucket_cnt, tp.dense, tp.light);
+                       (const uint32_t *)tp.totals, tp.bucket_cnt, tp.dense, tp.light);
     return hipGetLastError();
 }
 
