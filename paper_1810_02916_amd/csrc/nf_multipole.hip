@@ -13,7 +13,10 @@
 // particles (contiguous in the sorted array) are staged 128 at a time as
 // double powers x^k, y^k, z^k in LDS, and each thread sums its term over them
 // in sorted order, one cell segment at a time, writing one moment per cell
-// as it passes the cell's end.  Bound by the moment writes.
+// as it passes the cell's end.  A thread keeps two partial sums (particles at
+// even and odd staged positions) so that consecutive products do not wait on
+// each other, and adds them when the cell ends: the order is fixed by the
+// partition, so the moments are reproducible.
 #include "nf_internal.h"
 #include "nf_kernels.h"
 
@@ -30,7 +33,26 @@ constexpr int kPow = 3 * (kMaxOrder + 1);   // x^0..8, y^0..8, z^0..8 of one par
 // lies in [w kRange, (w + 1) kRange).  cost is increasing in c, so the first
 // cell of every range is found by one pass over the cells.
 constexpr int kCellCost = 8;
-constexpr int kRange = 2048;
+constexpr int kRange = 512;
+
+// (a, b, c) of each term at the largest order, in storage order; a lower
+// order p uses the first (p+1)(p+2)(p+3)/6 entries (the order is by degree).
+struct TermTable {
+    uint8_t a[kTermThreads], b[kTermThreads], c[kTermThreads];
+};
+constexpr TermTable make_terms() {
+    TermTable t{};
+    int k = 0;
+    for (int n = 0; n <= kMaxOrder; ++n)
+        for (int a = n; a >= 0; --a)
+            for (int b = n - a; b >= 0; --b, ++k) {
+                t.a[k] = (uint8_t)a;
+                t.b[k] = (uint8_t)b;
+                t.c[k] = (uint8_t)(n - a - b);
+            }
+    return t;
+}
+__constant__ TermTable kTerms = make_terms();
 
 __device__ __forceinline__ int64_t cell_cost(const int32_t *cs, int c) {
     return (int64_t)cs[c] + (int64_t)kCellCost * c;
@@ -62,7 +84,7 @@ k_multipoles(const DevBox *__restrict__ boxes, const int64_t *__restrict__ range
     // powers of the staged particles, particle-major: the threads of one
     // particle read 27 consecutive doubles (distinct banks)
     __shared__ double pw[kChunk][kPow];
-    __shared__ int cst[kRange / kCellCost + 1];   // cell starts of the range (<= 256 cells)
+    __shared__ int cst[kRange / kCellCost + 1];   // cell starts of the range (<= 64 cells)
     const int box = blockIdx.y;
     const int w = blockIdx.x;
     if ((int64_t)w >= range_base[box + 1] - range_base[box]) return;   // whole workgroup
@@ -70,19 +92,10 @@ k_multipoles(const DevBox *__restrict__ boxes, const int64_t *__restrict__ range
     const int32_t *f = first + range_base[box] + box;
     const int t = threadIdx.x;
     // (a, b, c) of this thread's term, as offsets into a particle's powers
-    int ia = 0, ib = kMaxOrder + 1, ic = 2 * (kMaxOrder + 1);
-    {
-        int k = 0;
-        for (int n = 0; n <= p; ++n)
-            for (int a = n; a >= 0; --a)
-                for (int b = n - a; b >= 0; --b, ++k)
-                    if (k == t) {
-                        ia = a;
-                        ib = kMaxOrder + 1 + b;
-                        ic = 2 * (kMaxOrder + 1) + (n - a - b);
-                    }
-    }
     const bool has_term = t < nterms;
+    const int ia = has_term ? kTerms.a[t] : 0;
+    const int ib = kMaxOrder + 1 + (has_term ? kTerms.b[t] : 0);
+    const int ic = 2 * (kMaxOrder + 1) + (has_term ? kTerms.c[t] : 0);
     const int32_t *__restrict__ cs = B.cell_start;
     const float4 *__restrict__ off = B.off;
     float *__restrict__ out = B.out;
@@ -95,7 +108,7 @@ k_multipoles(const DevBox *__restrict__ boxes, const int64_t *__restrict__ range
     const int p0 = cst[0], p1 = cst[c1 - c0];
     int cell = c0;            // current cell (uniform)
     int cend = cst[1];
-    double acc = 0.0;
+    double acc0 = 0.0, acc1 = 0.0;
     for (int s = p0; s < p1; s += kChunk) {
         const int e = min(s + kChunk, p1);
         if (s != p0) __syncthreads();   // the previous chunk is consumed
@@ -116,22 +129,28 @@ k_multipoles(const DevBox *__restrict__ boxes, const int64_t *__restrict__ range
         // segments of the chunk that lie in one cell (bounds are uniform)
         for (int i = s; i < e;) {
             while (i >= cend) {   // cells that end at or before particle i
-                if (has_term) out[(int64_t)cell * nterms + t] = (float)acc;
-                acc = 0.0;
+                if (has_term) out[(int64_t)cell * nterms + t] = (float)(acc0 + acc1);
+                acc0 = 0.0;
+                acc1 = 0.0;
                 ++cell;
                 cend = cst[cell - c0 + 1];
             }
             const int j = min(e, cend);
             const int lend = j - s;
-#pragma unroll 4
-            for (int l = i - s; l < lend; ++l)
-                acc = __fma_rn(pw[l][ia] * pw[l][ib], pw[l][ic], acc);
+            int l = i - s;
+#pragma unroll 2
+            for (; l + 1 < lend; l += 2) {
+                acc0 = __fma_rn(pw[l][ia] * pw[l][ib], pw[l][ic], acc0);
+                acc1 = __fma_rn(pw[l + 1][ia] * pw[l + 1][ib], pw[l + 1][ic], acc1);
+            }
+            if (l < lend) acc0 = __fma_rn(pw[l][ia] * pw[l][ib], pw[l][ic], acc0);
             i = j;
         }
     }
     for (; cell < c1; ++cell) {   // the last non-empty cell and trailing empty ones
-        if (has_term) out[(int64_t)cell * nterms + t] = (float)acc;
-        acc = 0.0;
+        if (has_term) out[(int64_t)cell * nterms + t] = (float)(acc0 + acc1);
+        acc0 = 0.0;
+        acc1 = 0.0;
     }
 }
 
