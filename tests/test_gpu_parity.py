@@ -257,6 +257,66 @@ def test_tile_paths_small_K_dense_and_sparse(K):
     assert err_stats(g, refg)["rms"] <= TOL_PLAIN
 
 
+def _box_with_counts(K, L, counts, seed):
+    """Cell c (linear order) holds counts[c % len(counts)] particles, uniform
+    inside the cell."""
+    rng = np.random.default_rng(seed)
+    h = L / K
+    parts = []
+    for c in range(K ** 3):
+        n = counts[c % len(counts)]
+        if n:
+            ijk = np.array([c // (K * K), (c // K) % K, c % K], dtype=np.float64)
+            parts.append((ijk + rng.uniform(0.0, 1.0, size=(n, 3))) * h)
+    pos = np.concatenate(parts)
+    return pos[rng.permutation(len(pos))]
+
+
+@pytest.mark.parametrize("dense_min", [41, 2])
+def test_tile_item_classes_by_cell_count(dense_min):
+    """Cells of every size around the item-class boundaries: remainders of
+    1..13 sinks (narrow items below 12, light items from 12), 40 and 41
+    (the default split between light and dense), and cells of 64 k plus such
+    a remainder, so one call mixes dense, light and narrow items."""
+    K, L = 9, 1.0
+    counts = [0, 1, 2, 3, 5, 7, 10, 11, 12, 13, 40, 41, 63, 64, 65, 75, 76, 129, 139]
+    pos = _box_with_counts(K, L, counts, seed=dense_min)
+    eps = 0.05 * L / K
+    b = nfp.bin_particles(_gpu(pos), K, L, eps)
+    b.set_dense_min(dense_min)
+    print(f"[classes] dense_min {dense_min} n {len(pos)}", flush=True)
+    ref = oracle.accel(pos, K, L, eps)
+    for comp in (False, True):
+        got = nfp.accel(b, 1.0, compensated=comp).cpu().numpy().astype(np.float64)
+        st = err_stats(got, ref)
+        print(dense_min, comp, st)
+        assert st["rms"] <= (TOL_COMP if comp else TOL_PLAIN), st
+    v = gaussian_cotangent(len(pos), 11 + dense_min).astype(np.float32)
+    g = nfp.accel_vjp(b, torch.from_numpy(v).to(DEV), 1.0, compensated=True).cpu().numpy()
+    refg = oracle.jvp(pos, K, L, eps, v.astype(np.float64))
+    assert err_stats(g, refg)["rms"] <= TOL_PLAIN
+
+
+def test_tile_all_items_narrow():
+    """A sparse box (at most 11 particles per cell): every item is narrow and
+    the dense and light kernels find empty queues."""
+    K, L = 16, 1.0
+    counts = [1, 4, 0, 11, 2, 7, 3, 9, 0, 5, 6, 10, 8]
+    pos = _box_with_counts(K, L, counts, seed=3)
+    eps = 0.05 * L / K
+    ref = oracle.accel(pos, K, L, eps)
+    print(f"[narrow] n {len(pos)}", flush=True)
+    for comp in (False, True):
+        got = _accel(pos, K, L, eps, compensated=comp)
+        st = err_stats(got, ref)
+        assert st["rms"] <= (TOL_COMP if comp else TOL_PLAIN), st
+    v = gaussian_cotangent(len(pos), 12).astype(np.float32)
+    b = nfp.bin_particles(_gpu(pos), K, L, eps)
+    g = nfp.accel_vjp(b, torch.from_numpy(v).to(DEV), 1.0, compensated=True).cpu().numpy()
+    refg = oracle.jvp(pos, K, L, eps, v.astype(np.float64))
+    assert err_stats(g, refg)["rms"] <= TOL_PLAIN
+
+
 @pytest.mark.parametrize("dense_min", [2, 17, 65])
 def test_tile_choice_dense_min(dense_min):
     """Every split between the two tile kernels gives the oracle's result:
