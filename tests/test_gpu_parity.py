@@ -431,3 +431,50 @@ def test_captured_graph_replays_match_eager():
     p0 = cf.positions[0].cpu().numpy()
     ref = oracle.accel(p0, specs[0].K, specs[0].L, specs[0].eps_s)
     assert err_stats(cf.out[0].cpu().numpy(), ref)["rms"] <= TOL_COMP
+
+
+def test_concurrent_callers_on_two_streams():
+    """Two host threads, each on a stream of its own, bin and evaluate
+    different boxes over and over (the library's side streams and events are
+    shared by the device's calls): every result equals, bitwise, the same
+    call made alone."""
+    import threading
+    names = ["uniform32k", "clustered262k"]
+    poss = [_gpu(make_box(WORKLOADS[n])) for n in names]
+    cots = [torch.from_numpy(gaussian_cotangent(WORKLOADS[n].n, 31).astype(np.float32)).to(DEV)
+            for n in names]
+
+    def run(i):
+        sp = WORKLOADS[names[i]]
+        b = nfp.bin_particles(poss[i], sp.K, sp.L, sp.eps_s)
+        return (nfp.accel(b, 1.0), nfp.accel(b, 1.0, compensated=True),
+                nfp.accel_vjp(b, cots[i], 1.0, compensated=True))
+
+    alone = [run(i) for i in range(2)]
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(device=DEV) for _ in range(2)]
+    results = [[], []]
+    errors = []
+
+    def worker(i):
+        try:
+            with torch.cuda.stream(streams[i]):
+                for _ in range(4):
+                    results[i].append(run(i))
+                streams[i].synchronize()
+        except Exception as e:   # surfaced below
+            errors.append(e)
+
+    print("[concurrent] two threads", flush=True)
+    ts = [threading.Thread(target=worker, args=(i,)) for i in range(2)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    torch.cuda.synchronize()
+    assert not errors, errors
+    for i in range(2):
+        assert len(results[i]) == 4
+        for r in results[i]:
+            for got, ref in zip(r, alone[i]):
+                assert torch.equal(got, ref), names[i]
