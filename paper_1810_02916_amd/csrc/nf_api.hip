@@ -91,6 +91,8 @@ struct Layout {
            light_off = 0, counter_off = 0;
     size_t stepio_off = 0, cellstat_off = 0, partial_off = 0;
     size_t mp_base_off = 0, mp_first_off = 0, mp_first_bytes = 0;
+    size_t mp_npieces_off = 0, mp_scan_off = 0, mp_pieces_off = 0, mp_partial_off = 0;
+    int64_t mp_max_pieces = 0;
     int64_t max_dense = 0;
     size_t total = 0;
     int64_t nblk = 0;
@@ -198,6 +200,18 @@ int validate(int nbox, const nf_box *boxes, Layout &L) {
         nranges += multipole_ranges(boxes[b].n, (int64_t)boxes[b].K * boxes[b].K * boxes[b].K) + 1;
     L.mp_first_bytes = 4 * (size_t)nranges;
     o = align_up(o + L.mp_first_bytes, 256);
+    // cells cut into pieces: counts then offsets, scan scratch, pieces, and
+    // the pieces' double moments at the largest order
+    L.mp_npieces_off = o;
+    o = align_up(o + 4 * (size_t)(L.C + 1), 256);
+    L.mp_scan_off = o;
+    o = align_up(o + 4 * (size_t)scan_scratch_words(L.C + 1), 256);
+    for (int b = 0; b < nbox; ++b) L.mp_max_pieces += multipole_max_pieces(boxes[b].n);
+    L.mp_pieces_off = o;
+    o = align_up(o + sizeof(MpPiece) * (size_t)L.mp_max_pieces, 256);
+    L.mp_partial_off = o;
+    o = align_up(o + 8 * (size_t)multipole_terms(multipole_max_order()) * (size_t)L.mp_max_pieces,
+                 256);
     L.total = std::max(std::max(std::max(bin_end, force_end), step_end), o);
     return NF_OK;
 }
@@ -498,17 +512,27 @@ int nf_multipoles(int nbox, const nf_box *boxes, int order, float *const *mom, v
             rbase[b + 1] = rbase[b] + r;
             max_ranges = std::max(max_ranges, r);
         }
-        if (max_ranges > INT32_MAX || (size_t)(rbase[nbox] + nbox) * 4 > L.mp_first_bytes)
+        if (max_ranges > INT32_MAX || L.mp_max_pieces > INT32_MAX ||
+            (size_t)(rbase[nbox] + nbox) * 4 > L.mp_first_bytes)
             return fail(NF_EUNSUPPORTED, "multipole partition exceeds the workspace plan");
         hipStream_t s = static_cast<hipStream_t>(stream);
         char *w = static_cast<char *>(ws);
         DevBox *d_tab = reinterpret_cast<DevBox *>(w + L.table_off);
         int64_t *d_rbase = reinterpret_cast<int64_t *>(w + L.mp_base_off);
-        int32_t *d_first = reinterpret_cast<int32_t *>(w + L.mp_first_off);
+        MpPlan mp;
+        mp.C = L.C;
+        mp.max_ncell = L.max_ncell;
+        mp.max_ranges = max_ranges;
+        mp.max_pieces = L.mp_max_pieces;
+        mp.range_base = d_rbase;
+        mp.first = reinterpret_cast<int32_t *>(w + L.mp_first_off);
+        mp.npieces = reinterpret_cast<uint32_t *>(w + L.mp_npieces_off);
+        mp.scan = reinterpret_cast<uint32_t *>(w + L.mp_scan_off);
+        mp.pieces = reinterpret_cast<MpPiece *>(w + L.mp_pieces_off);
+        mp.partial = reinterpret_cast<double *>(w + L.mp_partial_off);
         hipError_t e = upload(tab.data(), sizeof(DevBox) * tab.size(), d_tab, s);
         if (e == hipSuccess) e = upload(rbase.data(), sizeof(int64_t) * rbase.size(), d_rbase, s);
-        if (e == hipSuccess)
-            e = multipole_launch(d_tab, nbox, L.max_ncell, max_ranges, d_rbase, d_first, order, s);
+        if (e == hipSuccess) e = multipole_launch(d_tab, nbox, mp, order, s);
         if (e != hipSuccess) return fail(NF_EHIP, std::string("multipoles: ") + hipGetErrorString(e));
         g_last_error.clear();
         return NF_OK;

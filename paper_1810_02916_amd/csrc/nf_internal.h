@@ -7,6 +7,17 @@
 
 namespace nf {
 
+// Global-address-space view of a device pointer.  Pointers read from a
+// descriptor are generic, and generic (flat) loads and stores also count
+// against the counter that LDS accesses and scalar loads wait on: a kernel
+// that mixed them would wait for its global traffic at every such wait.
+template <class T>
+using gptr = __attribute__((address_space(1))) T *;
+template <class T>
+__device__ __forceinline__ gptr<T> gp(T *p) {
+    return (gptr<T>)p;
+}
+
 // Radix sort geometry: 8-bit digits, 256 threads per block, 16 keys per thread.
 constexpr int kDefaultDenseMin = 41;   // nf_box.dense_min == 0
 // Smallest float added to r^2 for Eq. 2: keeps rsq finite for coincident

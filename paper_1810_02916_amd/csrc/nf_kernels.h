@@ -53,11 +53,28 @@ int multipole_max_order();
 int multipole_terms(int p);
 // Workgroup ranges of one box (n particles, ncell cells).
 int64_t multipole_ranges(int64_t n, int64_t ncell);
-// d_range_base: [nbox + 1] prefix of the boxes' range counts; d_first:
-// sum over boxes of (ranges + 1) int32.
-hipError_t multipole_launch(const DevBox *d_boxes, int nbox, int64_t max_ncell,
-                            int64_t max_ranges, const int64_t *d_range_base, int32_t *d_first,
-                            int p, hipStream_t s);
+// Cells of more than multipole_big() particles are summed in pieces of at
+// most that many particles; a box of n particles has at most
+// multipole_max_pieces(n) pieces.
+int multipole_big();
+int64_t multipole_max_pieces(int64_t n);
+struct MpPiece {
+    int32_t box, cell, q0, q1, k, np;   // sorted slots [q0, q1); piece k of np
+};
+struct MpPlan {
+    int64_t C = 0;                  // cells over all boxes
+    int64_t max_ncell = 0;          // largest per-box cell count
+    int64_t max_ranges = 0;         // largest per-box range count
+    int64_t max_pieces = 0;         // bound on the pieces over all boxes
+    const int64_t *range_base = nullptr;   // [nbox + 1] prefix of the range counts
+    int32_t *first = nullptr;       // sum over boxes of (ranges + 1)
+    uint32_t *npieces = nullptr;    // [C + 1] pieces per cell, then their offsets
+    uint32_t *scan = nullptr;       // scan_scratch_words(C + 1)
+    MpPiece *pieces = nullptr;      // [max_pieces]
+    double *partial = nullptr;      // [max_pieces][terms] piece moments
+};
+hipError_t multipole_launch(const DevBox *d_boxes, int nbox, const MpPlan &mp, int p,
+                            hipStream_t s);
 
 // Time-step inputs and kick/drift (nf_step.hip).
 struct StepIO {                 // per box, caller order

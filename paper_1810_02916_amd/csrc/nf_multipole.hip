@@ -1,22 +1,22 @@
-// nf_multipole.hip -- per-cell multipole moments of the binned particles
-// (Sec. 2.1: the step that follows the near-field binning; double precision
-// inside, float storage; order p = 8 is the paper's usual choice).
+// One wave per workgroup.  Lane u owns a unit: a product x^a y^b and up to
+// four consecutive powers z^c0 .. z^(c0+3) of the same (a, b), so its terms
+// x^a y^b z^c share one product and walk up the z powers by multiplication
+// (61 units cover the 165 terms of order 8).  Particles are staged 32 at a
+// time as double powers x^k, y^k, z^k in LDS (the next 32 offsets are loaded
+// while the current ones are summed).
 //
-// Basis: complete Cartesian moments about the cell centre,
-//   M_abc(cell) = sum_{i in cell} x_i^a y_i^b z_i^c,   a + b + c <= p,
-// of the float cell offsets (cell widths) widened to double.  Terms are
-// stored per cell in degree order n = a + b + c, then a descending, then b
-// descending: T = (p+1)(p+2)(p+3)/6 floats per cell, cells in linear order.
-//
-// One workgroup thread per term.  A workgroup takes a run of consecutive
-// cells of bounded cost (particles plus a fixed cost per cell): their
-// particles (contiguous in the sorted array) are staged 128 at a time as
-// double powers x^k, y^k, z^k in LDS, and each thread sums its term over them
-// in sorted order, one cell segment at a time, writing one moment per cell
-// as it passes the cell's end.  A thread keeps two partial sums (particles at
-// even and odd staged positions) so that consecutive products do not wait on
-// each other, and adds them when the cell ends: the order is fixed by the
-// partition, so the moments are reproducible.
+//   k_multipoles  a run of consecutive cells of bounded cost (particles plus
+//                 a fixed cost per cell) per workgroup; each lane adds its
+//                 terms over the run's particles in sorted order, one cell
+//                 segment at a time, and writes a cell's moments as it passes
+//                 the cell's end.  Cells of more than kBig particles are
+//                 skipped: one workgroup summing them alone would set the
+//                 kernel's length.
+//   k_mp_pieces   those cells, cut into pieces of kBig particles, one piece
+//                 per workgroup, moments of the piece in double;
+//   k_mp_combine  adds a cell's pieces in piece order and writes its moments.
+// Every moment is a fixed sequence of double operations, so the moments are
+// reproducible.
 #include "nf_internal.h"
 #include "nf_kernels.h"
 
@@ -24,8 +24,8 @@ namespace nf {
 namespace {
 
 constexpr int kMaxOrder = 8;
-constexpr int kTermThreads = 192;   // >= (8+1)(8+2)(8+3)/6 = 165
-constexpr int kChunk = 128;         // particles staged per round
+constexpr int kUnitTerms = 4;       // consecutive z powers per lane
+constexpr int kChunk = 32;          // particles staged per round
 constexpr int kPow = 3 * (kMaxOrder + 1);   // x^0..8, y^0..8, z^0..8 of one particle
 // Work partition: cell c costs its particles plus kCellCost (its T stores);
 // workgroup w takes the cells whose cumulative cost
@@ -34,28 +34,18 @@ constexpr int kPow = 3 * (kMaxOrder + 1);   // x^0..8, y^0..8, z^0..8 of one par
 // cell of every range is found by one pass over the cells.
 constexpr int kCellCost = 8;
 constexpr int kRange = 512;
-
-// (a, b, c) of each term at the largest order, in storage order; a lower
-// order p uses the first (p+1)(p+2)(p+3)/6 entries (the order is by degree).
-struct TermTable {
-    uint8_t a[kTermThreads], b[kTermThreads], c[kTermThreads];
-};
-constexpr TermTable make_terms() {
-    TermTable t{};
-    int k = 0;
-    for (int n = 0; n <= kMaxOrder; ++n)
-        for (int a = n; a >= 0; --a)
-            for (int b = n - a; b >= 0; --b, ++k) {
-                t.a[k] = (uint8_t)a;
-                t.b[k] = (uint8_t)b;
-                t.c[k] = (uint8_t)(n - a - b);
-            }
-    return t;
-}
-__constant__ TermTable kTerms = make_terms();
+constexpr int kBig = 512;           // larger cells are summed in pieces of kBig
+constexpr int kMaxTerms = (kMaxOrder + 1) * (kMaxOrder + 2) * (kMaxOrder + 3) / 6;
 
 __device__ __forceinline__ int64_t cell_cost(const int32_t *cs, int c) {
     return (int64_t)cs[c] + (int64_t)kCellCost * c;
+}
+
+// Storage index of term (a, b, c), n = a + b + c: the terms of lower degree,
+// then a descending, then b descending within degree n.
+__device__ __forceinline__ int term_index(int a, int b, int c) {
+    const int n = a + b + c;
+    return n * (n + 1) * (n + 2) / 6 + (n - a) * (n - a + 1) / 2 + (n - a - b);
 }
 
 // first[w] = smallest c with cost(c) >= w kRange, for w = 0 .. nrange - 1,
@@ -78,12 +68,85 @@ k_mp_ranges(const DevBox *__restrict__ boxes, const int64_t *__restrict__ range_
     for (int64_t w = lo; w <= hi && w < nrange; ++w) f[w] = c;
 }
 
-__global__ void __launch_bounds__(kTermThreads)
+// This lane's unit: (a, b) pairs in order, each cut into runs of <= 4 z
+// powers; uk = 0 for a lane without a unit.  ia, ib, ic index a particle's
+// staged powers; idx are the storage indices of the unit's terms.
+struct LaneUnit {
+    int ia = 0, ib = kMaxOrder + 1, ic = 2 * (kMaxOrder + 1), uk = 0;
+    int idx[kUnitTerms] = {0, 0, 0, 0};
+};
+__device__ __forceinline__ LaneUnit lane_unit(int p, int t) {
+    int ua = 0, ub = 0, uc = 0, uk = 0;
+    int u = 0;
+    for (int a = 0; a <= p; ++a)
+        for (int b = 0; a + b <= p; ++b)
+            for (int c = 0; a + b + c <= p; c += kUnitTerms, ++u)
+                if (u == t) {
+                    ua = a;
+                    ub = b;
+                    uc = c;
+                    uk = min(kUnitTerms, p - a - b - c + 1);
+                }
+    LaneUnit L;
+    L.ia = ua;
+    L.ib = kMaxOrder + 1 + ub;
+    L.ic = 2 * (kMaxOrder + 1) + uc;
+    L.uk = uk;
+#pragma unroll
+    for (int j = 0; j < kUnitTerms; ++j) L.idx[j] = term_index(ua, ub, uc + j);
+    return L;
+}
+
+// Lane t < cnt writes the powers 0..p of its particle's offset o.
+__device__ __forceinline__ void stage_powers(double (*pw)[kPow], int t, int cnt, int p, float4 o) {
+    if (t < cnt) {
+        const double x = o.x, y = o.y, z = o.z;
+        double px = 1.0, py = 1.0, pz = 1.0;
+        for (int k = 0; k <= p; ++k) {
+            pw[t][k] = px;
+            pw[t][kMaxOrder + 1 + k] = py;
+            pw[t][2 * (kMaxOrder + 1) + k] = pz;
+            px *= x;
+            py *= y;
+            pz *= z;
+        }
+    }
+}
+
+// acc[j] += sum over staged particles l in [l0, l1), in order, of
+// x^a y^b z^(c0 + j).  Terms past the unit's last one are computed and never
+// stored.
+__device__ __forceinline__ void add_staged(const double (*pw)[kPow], int l0, int l1,
+                                           const LaneUnit &U, double acc[kUnitTerms]) {
+    constexpr int iz = 2 * (kMaxOrder + 1) + 1;   // z^1
+    // unrolled so that the loads and products of several particles are in
+    // flight at once; only the additions into acc chain
+#pragma unroll 4
+    for (int l = l0; l < l1; ++l) {
+        double m = pw[l][U.ia] * pw[l][U.ib];
+        m = m * pw[l][U.ic];
+        const double zz = pw[l][iz];
+        acc[0] += m;
+        m = m * zz;
+        acc[1] += m;
+        m = m * zz;
+        acc[2] += m;
+        m = m * zz;
+        acc[3] += m;
+    }
+}
+
+__device__ __forceinline__ int cell_count(const int *cst, int k) { return cst[k + 1] - cst[k]; }
+
+// The offset of sorted slot i (x, y, z) through a global pointer.
+__device__ __forceinline__ float4 ld_off(gptr<const float> off, int i) {
+    return make_float4(off[4 * i], off[4 * i + 1], off[4 * i + 2], 0.f);
+}
+
+__global__ void __launch_bounds__(64)
 k_multipoles(const DevBox *__restrict__ boxes, const int64_t *__restrict__ range_base,
              const int32_t *__restrict__ first, int p, int nterms) {
-    // powers of the staged particles, particle-major: the threads of one
-    // particle read 27 consecutive doubles (distinct banks)
-    __shared__ double pw[kChunk][kPow];
+    __shared__ double pw[kChunk][kPow];           // powers of the staged particles
     __shared__ int cst[kRange / kCellCost + 1];   // cell starts of the range (<= 64 cells)
     const int box = blockIdx.y;
     const int w = blockIdx.x;
@@ -91,66 +154,130 @@ k_multipoles(const DevBox *__restrict__ boxes, const int64_t *__restrict__ range
     const DevBox &B = boxes[box];
     const int32_t *f = first + range_base[box] + box;
     const int t = threadIdx.x;
-    // (a, b, c) of this thread's term, as offsets into a particle's powers
-    const bool has_term = t < nterms;
-    const int ia = has_term ? kTerms.a[t] : 0;
-    const int ib = kMaxOrder + 1 + (has_term ? kTerms.b[t] : 0);
-    const int ic = 2 * (kMaxOrder + 1) + (has_term ? kTerms.c[t] : 0);
-    const int32_t *__restrict__ cs = B.cell_start;
-    const float4 *__restrict__ off = B.off;
-    float *__restrict__ out = B.out;
+    const LaneUnit U = lane_unit(p, t);
+    const gptr<const int32_t> cs = gp(B.cell_start);
+    const gptr<const float> off = gp((const float *)B.off);
+    const gptr<float> out = gp(B.out);
     static_assert(kRange % kCellCost == 0, "range bound");
+    static_assert(kChunk <= 64, "one staged particle per lane");
     const int c0 = f[w], c1 = f[w + 1];
     if (c0 >= c1) return;
     // each cell costs >= kCellCost, so a range holds at most kRange / kCellCost cells
-    for (int k = t; k <= c1 - c0; k += kTermThreads) cst[k] = cs[c0 + k];
+    for (int k = t; k <= c1 - c0; k += 64) cst[k] = cs[c0 + k];
     __syncthreads();
-    const int p0 = cst[0], p1 = cst[c1 - c0];
-    int cell = c0;            // current cell (uniform)
-    int cend = cst[1];
-    double acc0 = 0.0, acc1 = 0.0;
-    for (int s = p0; s < p1; s += kChunk) {
-        const int e = min(s + kChunk, p1);
-        if (s != p0) __syncthreads();   // the previous chunk is consumed
-        if (t < e - s) {
-            const float4 o = off[s + t];
-            const double x = o.x, y = o.y, z = o.z;
-            double px = 1.0, py = 1.0, pz = 1.0;
-            for (int k = 0; k <= p; ++k) {
-                pw[t][k] = px;
-                pw[t][kMaxOrder + 1 + k] = py;
-                pw[t][2 * (kMaxOrder + 1) + k] = pz;
-                px *= x;
-                py *= y;
-                pz *= z;
+    double acc[kUnitTerms] = {0.0, 0.0, 0.0, 0.0};
+    auto flush = [&](int cell) {
+#pragma unroll
+        for (int j = 0; j < kUnitTerms; ++j) {
+            if (j < U.uk) out[(int64_t)cell * nterms + U.idx[j]] = (float)acc[j];
+            acc[j] = 0.0;
+        }
+    };
+    // runs [ca, cb) of cells of at most kBig particles (bounds are uniform)
+    for (int ca = c0; ca < c1;) {
+        if (cell_count(cst, ca - c0) > kBig) {
+            ++ca;
+            continue;
+        }
+        int cb = ca + 1;
+        while (cb < c1 && cell_count(cst, cb - c0) <= kBig) ++cb;
+        const int p0 = cst[ca - c0], p1 = cst[cb - c0];
+        int cell = ca;
+        int cend = cst[ca - c0 + 1];
+        float4 o = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (t < kChunk && p0 + t < p1) o = ld_off(off, p0 + t);
+        for (int s = p0; s < p1; s += kChunk) {
+            const int e = min(s + kChunk, p1);
+            __syncthreads();   // the previous chunk is consumed
+            stage_powers(pw, t, e - s, p, o);
+            if (t < kChunk && e + t < p1) o = ld_off(off, e + t);   // next chunk, in flight
+            __syncthreads();
+            for (int i = s; i < e;) {   // segments of the chunk that lie in one cell
+                while (i >= cend) {     // cells that end at or before particle i
+                    flush(cell);
+                    ++cell;
+                    cend = cst[cell - c0 + 1];
+                }
+                const int j = min(e, cend);
+                add_staged(pw, i - s, j - s, U, acc);
+                i = j;
             }
         }
-        __syncthreads();
-        // segments of the chunk that lie in one cell (bounds are uniform)
-        for (int i = s; i < e;) {
-            while (i >= cend) {   // cells that end at or before particle i
-                if (has_term) out[(int64_t)cell * nterms + t] = (float)(acc0 + acc1);
-                acc0 = 0.0;
-                acc1 = 0.0;
-                ++cell;
-                cend = cst[cell - c0 + 1];
-            }
-            const int j = min(e, cend);
-            const int lend = j - s;
-            int l = i - s;
-#pragma unroll 2
-            for (; l + 1 < lend; l += 2) {
-                acc0 = __fma_rn(pw[l][ia] * pw[l][ib], pw[l][ic], acc0);
-                acc1 = __fma_rn(pw[l + 1][ia] * pw[l + 1][ib], pw[l + 1][ic], acc1);
-            }
-            if (l < lend) acc0 = __fma_rn(pw[l][ia] * pw[l][ib], pw[l][ic], acc0);
-            i = j;
-        }
+        for (; cell < cb; ++cell) flush(cell);   // the run's last cells (and empty ones)
+        ca = cb;
     }
-    for (; cell < c1; ++cell) {   // the last non-empty cell and trailing empty ones
-        if (has_term) out[(int64_t)cell * nterms + t] = (float)(acc0 + acc1);
-        acc0 = 0.0;
-        acc1 = 0.0;
+}
+
+// Pieces per cell (0 for a cell of at most kBig particles).
+__global__ void __launch_bounds__(256)
+k_mp_count(const DevBox *__restrict__ boxes, uint32_t *__restrict__ npieces) {
+    const DevBox &B = boxes[blockIdx.y];
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    if (c >= B.ncell) return;
+    const gptr<const int32_t> cs = gp(B.cell_start);
+    const int n = cs[c + 1] - cs[c];
+    npieces[B.cellbase + c] = n > kBig ? (uint32_t)((n + kBig - 1) / kBig) : 0u;
+}
+
+// The pieces of each big cell at its offset (the exclusive scan of the counts).
+__global__ void __launch_bounds__(256)
+k_mp_emit(const DevBox *__restrict__ boxes, const uint32_t *__restrict__ offsets,
+          MpPiece *__restrict__ pieces, int64_t max_pieces) {
+    const DevBox &B = boxes[blockIdx.y];
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    if (c >= B.ncell) return;
+    const gptr<const int32_t> cs = gp(B.cell_start);
+    const int q = cs[c], n = cs[c + 1] - q;
+    if (n <= kBig) return;
+    const int np = (n + kBig - 1) / kBig;
+    const int64_t at = offsets[B.cellbase + c];
+    for (int k = 0; k < np && at + k < max_pieces; ++k)
+        pieces[at + k] = MpPiece{(int32_t)blockIdx.y, c, q + k * kBig, min(q + n, q + (k + 1) * kBig),
+                                 k, np};
+}
+
+__global__ void __launch_bounds__(64)
+k_mp_pieces(const DevBox *__restrict__ boxes, const MpPiece *__restrict__ pieces,
+            const uint32_t *__restrict__ total, double *__restrict__ partial, int p) {
+    __shared__ double pw[kChunk][kPow];
+    const int w = blockIdx.x;
+    if (w >= (int64_t)*total) return;   // whole workgroup
+    const MpPiece pc = pieces[w];
+    const DevBox &B = boxes[pc.box];
+    const int t = threadIdx.x;
+    const LaneUnit U = lane_unit(p, t);
+    const gptr<const float> off = gp((const float *)B.off);
+    double acc[kUnitTerms] = {0.0, 0.0, 0.0, 0.0};
+    float4 o = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (t < kChunk && pc.q0 + t < pc.q1) o = ld_off(off, pc.q0 + t);
+    for (int s = pc.q0; s < pc.q1; s += kChunk) {
+        const int e = min(s + kChunk, pc.q1);
+        __syncthreads();
+        stage_powers(pw, t, e - s, p, o);
+        if (t < kChunk && e + t < pc.q1) o = ld_off(off, e + t);
+        __syncthreads();
+        add_staged(pw, 0, e - s, U, acc);
+    }
+#pragma unroll
+    for (int j = 0; j < kUnitTerms; ++j)
+        if (j < U.uk) partial[(int64_t)w * kMaxTerms + U.idx[j]] = acc[j];
+}
+
+// The first piece of each big cell adds the cell's pieces in order.
+__global__ void __launch_bounds__(64)
+k_mp_combine(const DevBox *__restrict__ boxes, const MpPiece *__restrict__ pieces,
+             const uint32_t *__restrict__ total, const double *__restrict__ partial,
+             int nterms) {
+    const int w = blockIdx.x;
+    if (w >= (int64_t)*total) return;
+    const MpPiece pc = pieces[w];
+    if (pc.k != 0) return;
+    const DevBox &B = boxes[pc.box];
+    for (int t = threadIdx.x; t < nterms; t += 64) {
+        double sum = 0.0;
+        for (int k = 0; k < pc.np && w + k < (int)gridDim.x; ++k)
+            sum += partial[(int64_t)(w + k) * kMaxTerms + t];
+        gp(B.out)[(int64_t)pc.cell * nterms + t] = (float)sum;
     }
 }
 
@@ -164,15 +291,36 @@ int64_t multipole_ranges(int64_t n, int64_t ncell) {
     return (n + (int64_t)kCellCost * ncell) / kRange + 1;
 }
 
-hipError_t multipole_launch(const DevBox *d_boxes, int nbox, int64_t max_ncell,
-                            int64_t max_ranges, const int64_t *d_range_base, int32_t *d_first,
-                            int p, hipStream_t s) {
-    hipLaunchKernelGGL(k_mp_ranges, dim3((unsigned)((max_ncell + 1 + 255) / 256), (unsigned)nbox),
-                       dim3(256), 0, s, d_boxes, d_range_base, d_first);
+int multipole_big() { return kBig; }
+
+// Sum over big cells of ceil(n_c / kBig) <= n / kBig + (big cells) < 2 n / kBig.
+int64_t multipole_max_pieces(int64_t n) { return 2 * (n / kBig) + 1; }
+
+hipError_t multipole_launch(const DevBox *d_boxes, int nbox, const MpPlan &mp, int p,
+                            hipStream_t s) {
+    const dim3 cells((unsigned)((mp.max_ncell + 255) / 256), (unsigned)nbox);
+    hipLaunchKernelGGL(k_mp_ranges, dim3((unsigned)((mp.max_ncell + 1 + 255) / 256), (unsigned)nbox),
+                       dim3(256), 0, s, d_boxes, mp.range_base, mp.first);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_multipoles, dim3((unsigned)max_ranges, (unsigned)nbox), dim3(kTermThreads),
-                       0, s, d_boxes, d_range_base, (const int32_t *)d_first, p,
+    // big cells: counts, offsets (the last entry becomes the total), pieces
+    if ((e = fill_u32(mp.npieces, mp.C + 1, 0u, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_mp_count, cells, dim3(256), 0, s, d_boxes, mp.npieces);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = scan_exclusive(mp.npieces, mp.C + 1, mp.scan, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_mp_emit, cells, dim3(256), 0, s, d_boxes,
+                       (const uint32_t *)mp.npieces, mp.pieces, mp.max_pieces);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_multipoles, dim3((unsigned)mp.max_ranges, (unsigned)nbox), dim3(64), 0, s,
+                       d_boxes, mp.range_base, (const int32_t *)mp.first, p, multipole_terms(p));
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const uint32_t *total = mp.npieces + mp.C;
+    const unsigned gp = (unsigned)std::max<int64_t>(1, mp.max_pieces);
+    hipLaunchKernelGGL(k_mp_pieces, dim3(gp), dim3(64), 0, s, d_boxes,
+                       (const MpPiece *)mp.pieces, total, mp.partial, p);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_mp_combine, dim3(gp), dim3(64), 0, s, d_boxes,
+                       (const MpPiece *)mp.pieces, total, (const double *)mp.partial,
                        multipole_terms(p));
     return hipGetLastError();
 }

@@ -293,9 +293,9 @@ __device__ __forceinline__ float3 value(const Acc &a) {
 }
 
 __device__ __forceinline__ void store(const DevBox &B, int slot, float3 f) {
-    const int i = B.order[slot];
+    const int i = gp(B.order)[slot];
     if (i >= 0 && i < B.n) {   // always true for a consistent binning
-        float *o = B.out + 3 * (int64_t)i;
+        gptr<float> o = gp(B.out) + 3 * (int64_t)i;
         o[0] = f.x * B.scale;
         o[1] = f.y * B.scale;
         o[2] = f.z * B.scale;
@@ -361,16 +361,19 @@ k_dense(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
     const int lane = threadIdx.x;
     const int nitems = (int)totals[0];
     for (;;) {
-        if (lane == 0) s_item = (int)atomicAdd(counter, 1u);
+        if (lane == 0)
+            s_item = (int)__hip_atomic_fetch_add(gp(counter), 1u, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
         __syncthreads();
         const int itx = uni(s_item);
         __syncthreads();
         if (itx >= nitems) break;
-        const Item I = items[itx];
+        const gptr<const Item> ip = gp(items) + itx;
+        const Item I{ip->box, ip->cell0, ip->m, ip->chunk};
         const DevBox &B = boxes[I.box];
         const int K = B.K;
         const int cx = I.cell0 / (K * K), cy = (I.cell0 / K) % K, z = I.cell0 % K;
-        const int32_t *__restrict__ cs = B.cell_start;
+        const gptr<const int32_t> cs = gp(B.cell_start);
         const int s0 = uni(cs[I.cell0] + kUnit * I.chunk);
         const int g = uni(min(cs[I.cell0 + 1] - s0, kUnit));
         // Lanes beyond the g sinks repeat sink 0 and are dropped at the store:
@@ -378,9 +381,9 @@ k_dense(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
         // ranges when they are read back with readlane.
         const bool active = lane < g;
         const int slot = s0 + (active ? lane : 0);
-        const float4 oi = B.off[slot];
+        const float4 oi = ld_global4((gfloat *)B.off, slot);
         float4 vi = make_float4(0.f, 0.f, 0.f, 0.f);
-        if constexpr (MODE == 1) vi = cot_sorted[2 * (B.base + slot) + 1];
+        if constexpr (MODE == 1) vi = ld_global4((gfloat *)cot_sorted, 2 * (B.base + slot) + 1);
         const Coef k{B.cA, B.cB, B.cC, 2.0f * B.cC, B.eps * B.eps, B.r2floor};
         const bool fast = B.outer_newton != 0;
         const bool plummer = B.plummer != 0;   // Plummer law: one branch for every pair
@@ -516,7 +519,7 @@ k_light(const DevBox *__restrict__ boxes, const Item *__restrict__ all_items,
     __shared__ LightSmem<MODE, CAP, NT> sm;
     const int lane = threadIdx.x;   // 0 .. NT-1, all waves share the item
     const int nitems = (int)totals[cls];
-    const Item *__restrict__ items = all_items + (cls == 2 ? totals[1] : 0u);
+    const gptr<const Item> items = gp(all_items) + (cls == 2 ? totals[1] : 0u);
 
     // kQueues interleaved queues: workgroup w draws from queue q = w % kQueues,
     // whose k-th claim is item k * kQueues + q.  A single counter would cap
@@ -524,7 +527,8 @@ k_light(const DevBox *__restrict__ boxes, const Item *__restrict__ all_items,
     const int q = (int)(blockIdx.x % kQueues);
     uint32_t *qc = counter + kQueueStride * q;
     if (lane == 0) {
-        const int first = (int)atomicAdd(qc, 1u) * kQueues + q;
+        const int first = (int)__hip_atomic_fetch_add(gp(qc), 1u, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT) * kQueues + q;
         sm.item = first;
         if (first < nitems) {
             sm.ibox = items[first].box;
@@ -540,12 +544,13 @@ k_light(const DevBox *__restrict__ boxes, const Item *__restrict__ all_items,
         // claim the next item now (lane 0); its record is fetched once the setup
         // below is done, and both complete while this item runs
         int nxt = 0;
-        if (lane == 0) nxt = (int)atomicAdd(qc, 1u) * kQueues + q;
+        if (lane == 0)
+            nxt = (int)__hip_atomic_fetch_add(gp(qc), 1u, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT) * kQueues + q;
         const DevBox &B = boxes[ibox];
         const int K = B.K;
         const int cx = cell0 / (K * K), cy = (cell0 / K) % K, z = cell0 % K;
-        const int32_t *__restrict__ cs = B.cell_start;
-        const float4 *__restrict__ off = B.off;
+        const gptr<const int32_t> cs = gp(B.cell_start);
         gfloat *goff = (gfloat *)B.off;
         gfloat *gcot = (gfloat *)cot_sorted;
         const int s0 = uni(cs[cell0]) + kUnit * chunk;
@@ -558,9 +563,9 @@ k_light(const DevBox *__restrict__ boxes, const Item *__restrict__ all_items,
         const bool active = lane < g * P;
         const int a = active ? lane % g : 0;
         const int b = active ? lane / g : 0;
-        const float4 oi = off[s0 + a];
+        const float4 oi = ld_global4((gfloat *)B.off, s0 + a);
         float4 vi = make_float4(0.f, 0.f, 0.f, 0.f);
-        if constexpr (MODE == 1) vi = cot_sorted[2 * (B.base + s0 + a) + 1];
+        if constexpr (MODE == 1) vi = ld_global4((gfloat *)cot_sorted, 2 * (B.base + s0 + a) + 1);
 
         // ---- pieces and run table: wave 0, one lane per row.  Staged layout: the
         //      inner parts of rows 0..24, then their outer parts; the non-empty

@@ -67,3 +67,31 @@ def test_multipoles_batched_and_empty_box():
         absm = oracle.abs_moments(pos, K, L, 6)
         tol = 2.0 ** -22 * np.abs(ref32.astype(np.float64)) + 1e-12 * absm
         assert (np.abs(g - ref32) <= tol).all()
+
+
+@pytest.mark.parametrize("p", [1, 8])
+def test_multipoles_big_cells_in_pieces(p):
+    """Cells above the piece size are summed in pieces and combined: cells of
+    exactly one piece (512), one past it (513), two pieces (1024), one past
+    (1025) and many (5000), next to small and empty cells, in two boxes of
+    one batch."""
+    K, L = 6, 1.0
+    h = L / K
+    rng = np.random.default_rng(90 + p)
+    sizes = {(0, 0, 0): 512, (0, 0, 1): 513, (2, 5, 5): 1024, (3, 3, 3): 1025, (5, 5, 4): 5000,
+             (1, 1, 1): 7}
+    parts = [(np.array(c) + rng.uniform(0, 1, size=(n, 3))) * h for c, n in sizes.items()]
+    pos = np.concatenate(parts + [rng.uniform(0, L, size=(300, 3))])
+    pos = pos[rng.permutation(len(pos))]
+    _check(pos, K, L, p)
+    other = clustered_box(4000, 12, 7, 1.0, 1.5, 0.5, seed=9)
+    b = nfp.bin_particles_batched([torch.from_numpy(other).to(DEV), torch.from_numpy(pos).to(DEV)],
+                                  [7, K], [1.0, L], [0.01, 0.01])
+    got = nfp.multipoles(b, p)
+    for (q, KK, LL), g in zip([(other, 7, 1.0), (pos, K, L)], got):
+        ref, ref32 = oracle.multipoles(q, KK, LL, p)
+        absm = oracle.abs_moments(q, KK, LL, p)
+        tol = 2.0 ** -22 * np.abs(ref32.astype(np.float64)) + 1e-12 * absm
+        g = g.cpu().numpy().astype(np.float64)
+        np.testing.assert_array_equal(g[:, 0], ref[:, 0])
+        assert (np.abs(g - ref32) <= tol).all()
