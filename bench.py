@@ -44,14 +44,41 @@ def parse():
     return ap.parse_args()
 
 
+def _code_tokens(text: str) -> str:
+    """C++ source without comments and with whitespace runs collapsed, so
+    that a comment-only edit leaves the hash unchanged (string and character
+    literals are kept as written)."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c == "/" and text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif c == "/" and text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        elif c in "\"'":
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def kernel_source_hash() -> str:
-    """Hash of the HIP sources, to tell whether stored counters are current."""
+    """Hash of the HIP sources' code (comments and layout ignored), to tell
+    whether stored counters are current."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1810_02916_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(f.encode() + b"\0" + fh.read())
+        with open(os.path.join(csrc, f), encoding="utf-8") as fh:
+            h.update(f.encode() + b"\0" + _code_tokens(fh.read()).encode())
     return h.hexdigest()[:16]
 
 
@@ -293,7 +320,7 @@ def main():
                      "traffic": stored_traffic(sp.name, dom),
                      "flop_per_pair": fdom, "pairs_per_launch": I,
                      "timed": "HIP events around the library call on its stream: planner "
-                              "kernels + dense and light force kernels"},
+                              "kernels + dense, light and narrow force kernels"},
         "kernel_source_hash": kernel_source_hash(),
         "extras": extras,
     }

@@ -858,7 +858,7 @@ template <int MODE, bool COMP>
 hipError_t launch_force(const DevBox *d_boxes, const TilePlan &tp, const float4 *cot,
                         hipStream_t s) {
     constexpr int CAP = MODE == 0 ? 1024 : 768;
-    constexpr int NCAP = MODE == 0 ? 256 : 192;   // narrow items: 4.5 KB windows
+    constexpr int NCAP = MODE == 0 ? 256 : 192;   // narrow items: 4 KB windows (4.5 KB, VJP)
     static const int gd = persistent_grid(k_dense<MODE, COMP>, kUnit);
     // every queue needs at least one workgroup: the grids are multiples of kQueues
     static const int gl =
