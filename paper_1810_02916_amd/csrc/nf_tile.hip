@@ -56,7 +56,7 @@ __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlan
 // ------------------------------------------------------------------ planner
 
 // Sources in the 5x5x5 block of cell (cx, cy, cz): 25 row ranges of 5 cells.
-__device__ int block_sources(const int32_t *cs, int K, int cx, int cy, int cz) {
+__device__ int block_sources(gptr<const int32_t> cs, int K, int cx, int cy, int cz) {
     int s = 0;
     for (int r = 0; r < kRows; ++r) {
         const int rb = (wrapk(cx + r / 5 - 2, K) * K + wrapk(cy + r % 5 - 2, K)) * K;
@@ -105,13 +105,14 @@ k_plan_count(const DevBox *boxes, uint32_t *cellinfo, uint32_t *bucket_cnt) {
     const DevBox &B = boxes[blockIdx.y];
     const int c = blockIdx.x * 256 + threadIdx.x;
     if (c < B.ncell) {
-        const int n = B.cell_start[c + 1] - B.cell_start[c];
+        const gptr<const int32_t> cs = gp(B.cell_start);
+        const int n = cs[c + 1] - cs[c];
         uint32_t info = 0;
         if (n > 0) {
-            const int K = B.K;
-            const float S = (float)block_sources(B.cell_start, K, c / (K * K), (c / K) % K, c % K);
             const CellItems it = cell_items(n, B.dense_min);
-            if (it.ndense) {
+            if (it.ndense) {   // S (the block's sources) ranks dense items only
+                const int K = B.K;
+                const float S = (float)block_sources(cs, K, c / (K * K), (c / K) % K, c % K);
                 const int b = cost_bucket(S);
                 atomicAdd(&h[b], (uint32_t)it.ndense);
                 info |= (uint32_t)(b + 1);
@@ -167,7 +168,7 @@ k_plan_emit(const DevBox *boxes, const uint32_t *__restrict__ cellinfo,
     if (c < B.ncell) {
         info = cellinfo[B.cellbase + c];
         if (info) {
-            n = B.cell_start[c + 1] - B.cell_start[c];
+            n = gp(B.cell_start)[c + 1] - gp(B.cell_start)[c];
             it = cell_items(n, B.dense_min);
             bd = (int)(info & 0xffffu) - 1;
             bl = (int)(info >> 16) - 1;
