@@ -33,3 +33,4 @@ def test_package_never_imports_the_oracle():
                 assert "nf_oracle" not in text and "liboracle" not in text, f
     for f in os.listdir(os.path.join(ROOT, "include")):
         assert "oracle" not in open(os.path.join(ROOT, "include", f)).read().lower(), f
+
