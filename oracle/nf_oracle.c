@@ -345,14 +345,15 @@ int oracle_accel(int64_t n, const double *pos, int32_t K, double L, double eps_s
  *   (J t)_i = gm kappa^3 sum_{j in N(i)} Jhat(r_ij) (t_j - t_i)
  * where Jhat = dF/dr in cell units and the cell assignment is held fixed.
  * tvec and out are [n][3] in input order (out: [nsink][3] if sinks given).
+ * round_offsets as in oracle_accel.
  */
 int oracle_jvp(int64_t n, const double *pos, int32_t K, double L, double eps_s,
-               double gm, int law, const double *tvec, int64_t nsink, const int64_t *sinks,
-               double *out) {
+               double gm, int law, int round_offsets, const double *tvec, int64_t nsink,
+               const int64_t *sinks, double *out) {
     if (!(eps_s > 0) || !isfinite(eps_s) || !isfinite(gm) || law < 0 || law > 1)
         return OR_EINVAL;
     binned_t b;
-    int rc = binned_build(&b, n, pos, K, L, 0);
+    int rc = binned_build(&b, n, pos, K, L, round_offsets);
     if (rc != OR_OK) return rc;
     const double eps = eps_s * b.kappa;
     const double scale = gm * b.kappa * b.kappa * b.kappa;
@@ -390,13 +391,14 @@ int oracle_jvp(int64_t n, const double *pos, int32_t K, double L, double eps_s,
  * with d a_i/d x_j = gm kappa^3 Jhat(r_ij) for j != i and
  *      d a_i/d x_i = -gm kappa^3 sum_j Jhat(r_ij).
  * Serial (it scatters into shared outputs).  v and out are [n][3], input order.
+ * round_offsets as in oracle_accel.
  */
 int oracle_vjp(int64_t n, const double *pos, int32_t K, double L, double eps_s,
-               double gm, int law, const double *v, double *out) {
+               double gm, int law, int round_offsets, const double *v, double *out) {
     if (!(eps_s > 0) || !isfinite(eps_s) || !isfinite(gm) || law < 0 || law > 1)
         return OR_EINVAL;
     binned_t b;
-    int rc = binned_build(&b, n, pos, K, L, 0);
+    int rc = binned_build(&b, n, pos, K, L, round_offsets);
     if (rc != OR_OK) return rc;
     const double eps = eps_s * b.kappa;
     const double scale = gm * b.kappa * b.kappa * b.kappa;

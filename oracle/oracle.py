@@ -50,8 +50,8 @@ def _get():
         lib.oracle_bin.argtypes = [i64, vp, i32, dbl, vp, vp, vp]
         ci = ctypes.c_int
         lib.oracle_accel.argtypes = [i64, vp, i32, dbl, dbl, dbl, ci, ci, i64, vp, vp, vp]
-        lib.oracle_jvp.argtypes = [i64, vp, i32, dbl, dbl, dbl, ci, vp, i64, vp, vp]
-        lib.oracle_vjp.argtypes = [i64, vp, i32, dbl, dbl, dbl, ci, vp, vp]
+        lib.oracle_jvp.argtypes = [i64, vp, i32, dbl, dbl, dbl, ci, ci, vp, i64, vp, vp]
+        lib.oracle_vjp.argtypes = [i64, vp, i32, dbl, dbl, dbl, ci, ci, vp, vp]
         lib.oracle_interactions.argtypes = [i64, vp, i32, dbl, vp]
         lib.oracle_num_threads.restype = ctypes.c_int
         lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
@@ -136,7 +136,10 @@ def accel(pos, K: int, L: float, eps_s: float, gm: float = 1.0, *,
 
 
 def jvp(pos, K: int, L: float, eps_s: float, tvec, gm: float = 1.0, *, sinks=None,
-        law: str = "spline"):
+        law: str = "spline", round_offsets: bool = False):
+    """Jacobian-vector product (gather form), FP64, binning frozen.
+    ``round_offsets``: evaluate on the float-rounded cell offsets (the GPU's
+    input representation) instead of the exact double offsets."""
     p = _pos(pos)
     n = p.shape[0]
     t = _pos(tvec)
@@ -144,17 +147,19 @@ def jvp(pos, K: int, L: float, eps_s: float, tvec, gm: float = 1.0, *, sinks=Non
     m = n if s is None else s.shape[0]
     out = np.empty((m, 3), dtype=np.float64)
     _check(_get().oracle_jvp(n, _p(p), int(K), float(L), float(eps_s), float(gm), _law(law),
-                             _p(t), m, _p(s), _p(out)), "oracle_jvp")
+                             1 if round_offsets else 0, _p(t), m, _p(s), _p(out)), "oracle_jvp")
     return out
 
 
-def vjp(pos, K: int, L: float, eps_s: float, v, gm: float = 1.0, *, law: str = "spline"):
+def vjp(pos, K: int, L: float, eps_s: float, v, gm: float = 1.0, *, law: str = "spline",
+        round_offsets: bool = False):
+    """Vector-Jacobian product (scatter form, written from the chain rule)."""
     p = _pos(pos)
     n = p.shape[0]
     vv = _pos(v)
     out = np.empty((n, 3), dtype=np.float64)
     _check(_get().oracle_vjp(n, _p(p), int(K), float(L), float(eps_s), float(gm), _law(law),
-                             _p(vv), _p(out)), "oracle_vjp")
+                             1 if round_offsets else 0, _p(vv), _p(out)), "oracle_vjp")
     return out
 
 

@@ -460,3 +460,118 @@ def test_spline_plummer_equal_minimum_dynamical_time():
     eps_s = 2.16 * eps_p
     gs = [_two_body(u * eps_s, eps_s)[0, 0] / (u * eps_s) for u in (1e-6, 0.2, 0.5, 0.9, 1.5)]
     assert all(a > b for a, b in zip(gs, gs[1:]))
+
+
+# ------------------------------------------------------------------ rounded offsets and sink subsets
+
+def _snapped_box(n, K, seed):
+    """Positions in a box of side 1 with K a power of two, so that x * K is
+    exact; offsets drawn in [-0.49, 0.49] (a float-rounded offset then stays
+    inside its cell)."""
+    rng = np.random.default_rng(seed)
+    c = rng.integers(0, K, size=(n, 3)).astype(np.float64)
+    o = rng.uniform(-0.49, 0.49, size=(n, 3))
+    return (c + 0.5 + o) / K
+
+
+def test_round_offsets_mode_equals_exact_oracle_on_snapped_positions():
+    """The rounded-offset mode (Sec. 4.5: the single-precision state judged
+    against double precision) evaluates the exact oracle on positions moved
+    to (c + 1/2 + fl32(o)) / kappa, which are representable exactly when
+    kappa is a power of two: accelerations, JVP and VJP agree bitwise with
+    the exact mode run on those moved positions, and differ from the exact
+    mode on the original ones."""
+    K, L, eps = 16, 1.0, 0.05 / 16
+    pos = _snapped_box(3000, K, 41)
+    cell, o = oracle.cells(pos, K, L)
+    snapped = (cell + 0.5 + o.astype(np.float32).astype(np.float64)) / K
+    c2, o2 = oracle.cells(snapped, K, L)
+    np.testing.assert_array_equal(c2, cell)
+    np.testing.assert_array_equal(o2, o.astype(np.float32).astype(np.float64))
+    t = gaussian_cotangent(len(pos), 42)
+    for law, e in (("spline", eps), ("plummer", eps / 2.16)):
+        r = oracle.accel(pos, K, L, e, law=law, round_offsets=True)
+        assert r.tobytes() == oracle.accel(snapped, K, L, e, law=law).tobytes()
+        assert not np.array_equal(r, oracle.accel(pos, K, L, e, law=law))
+        rj = oracle.jvp(pos, K, L, e, t, law=law, round_offsets=True)
+        assert rj.tobytes() == oracle.jvp(snapped, K, L, e, t, law=law).tobytes()
+        rv = oracle.vjp(pos, K, L, e, t, law=law, round_offsets=True)
+        assert rv.tobytes() == oracle.vjp(snapped, K, L, e, t, law=law).tobytes()
+        assert not np.array_equal(rj, oracle.jvp(pos, K, L, e, t, law=law))
+
+
+def test_sink_subset_equals_full_evaluation():
+    """The sink-subset path that the full-size parity tests and the benchmark
+    use returns, bitwise, the rows of the full evaluation (any order,
+    repeats allowed), for both laws and both offset modes."""
+    K, L, eps = 7, 1.0, 0.03 / 7
+    pos = clustered_box(3000, 14, K, L, 1.5, 0.5, seed=17)
+    t = gaussian_cotangent(len(pos), 18)
+    rng = np.random.default_rng(19)
+    sinks = np.concatenate([rng.choice(len(pos), 200, replace=False), [5, 5, 0, len(pos) - 1]])
+    for law in ("spline", "plummer"):
+        for ro in (False, True):
+            full = oracle.accel(pos, K, L, eps, law=law, round_offsets=ro)
+            sub, cnt = oracle.accel(pos, K, L, eps, law=law, round_offsets=ro, sinks=sinks,
+                                    return_count=True)
+            assert sub.tobytes() == full[sinks].tobytes()
+            fullj = oracle.jvp(pos, K, L, eps, t, law=law, round_offsets=ro)
+            subj = oracle.jvp(pos, K, L, eps, t, law=law, round_offsets=ro, sinks=sinks)
+            assert subj.tobytes() == fullj[sinks].tobytes()
+    # the subset's interaction count is the sum of its sinks' block counts
+    cell, _ = oracle.cells(pos, K, L)
+    d = np.mod(cell[None, :, :] - cell[sinks][:, None, :] + 2, K) - 2
+    assert cnt == int(np.all(np.abs(d) <= 2, axis=2).sum())
+    with pytest.raises(oracle.OracleError):
+        oracle.accel(pos, K, L, eps, sinks=[len(pos)])
+
+
+def _tile_box(K):
+    """The boxes of the GPU tile tests: a clustered box of 6 particles per
+    cell plus two cells of 300 and 150 particles at z = 0 and z = K-1."""
+    rng = np.random.default_rng(100 + K)
+    L, h = 1.0, 1.0 / K
+    base = clustered_box(K ** 3 * 6, 2 * K, K, L, 1.5, 0.5, seed=K)
+    dense = (np.array([1, K - 1, 0]) + rng.uniform(0, 1, size=(300, 3))) * h
+    dense2 = (np.array([2, 2, K - 1]) + rng.uniform(0, 1, size=(150, 3))) * h
+    pos = np.concatenate([base, dense, dense2])[rng.permutation(len(base) + 450)]
+    return pos, L, 0.03 * h
+
+
+def _floor(a_exact, a_round):
+    return float(np.sqrt(((a_round - a_exact) ** 2).sum() / (a_exact ** 2).sum()))
+
+
+@pytest.mark.parametrize("K", [5, 6, 7, 9, 13])
+def test_vjp_representation_floor_band(K):
+    """Reading of the VJP tolerance: rounding the offsets to float alone
+    (no FP32 arithmetic at all) moves the VJP by 0.4-3e-6 rms on these
+    boxes, more than it moves the accelerations, because the Jacobian of
+    Eq. 2 carries one more power of 1/r than the force.  An end-to-end VJP
+    gate at 1e-6 is therefore below what any kernel on float offsets can
+    reach; the GPU tests gate the kernel's own error against the oracle on
+    the same float offsets, and the end-to-end error at max(1e-6, 2 x floor)."""
+    pos, L, eps = _tile_box(K)
+    t = gaussian_cotangent(len(pos), 7 * K).astype(np.float32).astype(np.float64)
+    fv = _floor(oracle.jvp(pos, K, L, eps, t), oracle.jvp(pos, K, L, eps, t, round_offsets=True))
+    fa = _floor(oracle.accel(pos, K, L, eps), oracle.accel(pos, K, L, eps, round_offsets=True))
+    print(K, "vjp floor", fv, "accel floor", fa)
+    assert 4e-7 <= fv <= 3e-6
+    assert fv > fa
+
+
+def test_vjp_representation_floor_clustered262k():
+    """The same floor on the 64^3 clustered box the VJP parity tests use:
+    0.4-1.5e-6 rms for the VJP, an order of magnitude above the
+    accelerations' floor on that box."""
+    from paper_1810_02916_amd.synth import WORKLOADS, make_box
+    sp = WORKLOADS["clustered262k"]
+    pos = make_box(sp)
+    t = gaussian_cotangent(sp.n, 1815 * 10 + 2).astype(np.float32).astype(np.float64)
+    fv = _floor(oracle.jvp(pos, sp.K, sp.L, sp.eps_s, t),
+                oracle.jvp(pos, sp.K, sp.L, sp.eps_s, t, round_offsets=True))
+    fa = _floor(oracle.accel(pos, sp.K, sp.L, sp.eps_s),
+                oracle.accel(pos, sp.K, sp.L, sp.eps_s, round_offsets=True))
+    print("clustered262k vjp floor", fv, "accel floor", fa)
+    assert 4e-7 <= fv <= 1.5e-6
+    assert fv > 5 * fa
