@@ -146,7 +146,7 @@ __global__ void __launch_bounds__(256) k_vjp_simple(const DevBox *boxes,
     const int c = find_cell(cs, B.ncell, s);
     const int cz = c % K, cy = (c / K) % K, cx = c / (K * K);
     const float4 oi = off[s];
-    const float4 vi = cv[2 * s + 1];
+    const float4 vi = cv[2 * (int64_t)s + 1];
     const float cA = B.cA, cB = B.cB, cC2 = 2.0f * B.cC, cC = B.cC;
     const float eps2 = B.eps * B.eps;
     const bool fast = B.outer_newton != 0;
@@ -168,7 +168,7 @@ __global__ void __launch_bounds__(256) k_vjp_simple(const DevBox *boxes,
                                                         dy == 2 || dz == -2 || dz == 2));
                 for (int j = j0; j < j1; ++j) {
                     const float4 oj = off[j];
-                    const float4 vj = cv[2 * j + 1];
+                    const float4 vj = cv[2 * (int64_t)j + 1];
                     const float rx = oj.x - sx, ry = oj.y - sy, rz = oj.z - sz;
                     const float ux = vj.x - vi.x, uy = vj.y - vi.y, uz = vj.z - vi.z;
                     float r2 = __builtin_fmaf(rx, rx, floor2);

@@ -140,7 +140,8 @@ __device__ __forceinline__ int cell_count(const int *cst, int k) { return cst[k 
 
 // The offset of sorted slot i (x, y, z) through a global pointer.
 __device__ __forceinline__ float4 ld_off(gptr<const float> off, int i) {
-    return make_float4(off[4 * i], off[4 * i + 1], off[4 * i + 2], 0.f);
+    const gptr<const float> q = off + 4 * (int64_t)i;   // 4 i passes 2^31 for i >= 2^29
+    return make_float4(q[0], q[1], q[2], 0.f);
 }
 
 __global__ void __launch_bounds__(64)

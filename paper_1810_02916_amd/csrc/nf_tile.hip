@@ -310,10 +310,13 @@ typedef float rec8 __attribute__((ext_vector_type(8)));
 typedef const __attribute__((address_space(4))) rec8 crec8;
 typedef const __attribute__((address_space(1))) float gfloat;
 
-// A float4 of a global array through a global-address-space pointer (plain
-// pointers loaded from a descriptor compile to flat loads).
-__device__ __forceinline__ float4 ld_global4(gfloat *p, int i) {
-    return make_float4(p[4 * i], p[4 * i + 1], p[4 * i + 2], p[4 * i + 3]);
+// Float4 number i of a global array through a global-address-space pointer
+// (plain pointers loaded from a descriptor compile to flat loads).  The index
+// is 64-bit: VJP records are addressed by 2 (base + slot), which exceeds 2^31
+// once the boxes of a call hold more than 2^30 particles.
+__device__ __forceinline__ float4 ld_global4(gfloat *p, int64_t i) {
+    gfloat *q = p + 4 * i;
+    return make_float4(q[0], q[1], q[2], q[3]);
 }
 
 // Sources [j0, j1) of one cell through scalar loads.
@@ -333,8 +336,8 @@ __device__ __forceinline__ void run_scalar(cfloat *__restrict__ src, cfloat *__r
 #pragma unroll(MODE == 0 ? 4 : 2)
         for (int t = 0; t < blk; ++t, ++j) {
             if constexpr (MODE == 0) {
-                pair_accel<SPLINE>(src[4 * j], src[4 * j + 1], src[4 * j + 2], xs, ys, zs, k, px,
-                                   py, pz);
+                cfloat *sj = src + 4 * (int64_t)j;   // 64-bit: 4 j passes 2^31 for j >= 2^29
+                pair_accel<SPLINE>(sj[0], sj[1], sj[2], xs, ys, zs, k, px, py, pz);
             } else {
                 // one 32-byte record per source (offset, cotangent), one scalar load
                 const rec8 r8 = ((crec8 *)src)[j];

@@ -151,3 +151,22 @@ def test_stepping_calls_reject_bad_arguments(lib):
     assert L.nf_kick_drift(1, good, p1, p1, p1, float("nan"), 0.1, ws, 1 << 20, None) == lib.NF_EINVAL
     assert L.nf_kick_drift(1, good, p1, p1, nul, 0.1, 0.1, ws, 1 << 20, None) == lib.NF_EINVAL
     assert L.nf_kick_drift(1, good, p1, p1, p1, 0.1, 0.1, ws, 16, None) == lib.NF_EWORKSPACE
+
+
+def test_size_limits_of_the_32bit_index_range(lib):
+    """Per-box and total particle counts up to 2^31 - 1 are accepted (device
+    offsets and record indices are 64-bit where 4 n or 2 N passes 2^31);
+    beyond that the calls return NF_EUNSUPPORTED before touching a device."""
+    L = lib.load()
+    top = (1 << 31) - 1
+    ok = (lib.NfBox * 1)(_box(lib, top, 8))
+    assert L.nf_workspace_bytes(1, ok, 0) > 32 * top
+    over = (lib.NfBox * 1)(_box(lib, top + 1, 8))
+    assert L.nf_workspace_bytes(1, over, 0) == 0
+    assert "2^31" in lib.last_error()
+    two = (lib.NfBox * 2)(_box(lib, 1 << 30, 8), _box(lib, 1 << 30, 8))
+    assert L.nf_workspace_bytes(2, two, 0) == 0
+    assert "total particles" in lib.last_error()
+    outs = (ctypes.c_void_p * 1)(0x2000)
+    assert L.nf_accel(1, over, 1.0, 0, outs, ctypes.c_void_p(0x100000), 1 << 20,
+                      None) == lib.NF_EUNSUPPORTED
