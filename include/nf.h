@@ -92,6 +92,9 @@ enum {
 /* Upper bound on boxes per call. */
 #define NF_MAX_BOXES 4096
 
+/* Size of the static scratch array of nf_accel_noalloc, per GPU (32 MiB). */
+#define NF_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+
 /* Highest multipole order of nf_multipoles. */
 #define NF_MAX_ORDER 8
 
@@ -172,6 +175,28 @@ int nf_bin_particles(int nbox, const nf_box *boxes, void *ws, size_t ws_bytes,
  */
 int nf_accel(int nbox, const nf_box *boxes, double gm, uint32_t flags,
              float *const *acc, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Allocation-free nf_accel, for callers that cannot allocate device memory or
+ * hand over a workspace: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments and results as nf_accel,
+ * bitwise, without ws / ws_bytes: the call's scratch (descriptor table,
+ * planner tables, work items, queue counters) is a static device array of
+ * NF_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on
+ * until the process ends.  The first call on a device looks up that device's
+ * copy of the array (hipGetSymbolAddress); no call allocates device memory.
+ * The dense, light and narrow kernels run one after another on `stream`.
+ * Limit: calls whose scratch exceeds NF_NOALLOC_SCRATCH_BYTES return
+ * NF_EUNSUPPORTED with nothing enqueued; the scratch is about 20 bytes per
+ * cell plus 16 bytes per 41 particles plus 9 KB (a box of 64^3 cells and
+ * 2^21 particles needs about 6 MiB; 2^20 cells is the largest grid that fits).
+ * Every call on one GPU shares that GPU's array and leaves its contents
+ * there (each call clears what it needs zeroed): calls that overlap on one
+ * GPU, on other streams or host threads, race and must be ordered by the
+ * caller.
+ */
+int nf_accel_noalloc(int nbox, const nf_box *boxes, double gm, uint32_t flags,
+                     float *const *acc, void *stream);
 
 /*
  * Vector-Jacobian product of the accelerations with respect to positions,

@@ -24,6 +24,7 @@ NF_SPLINE_EVERYWHERE = 1 << 3
 
 NF_MAX_BOXES = 4096
 NF_MAX_ORDER = 8
+NF_NOALLOC_SCRATCH_BYTES = 32 << 20
 
 EXPORTED = (
     "nf_version",
@@ -32,6 +33,7 @@ EXPORTED = (
     "nf_workspace_bytes",
     "nf_bin_particles",
     "nf_accel",
+    "nf_accel_noalloc",
     "nf_accel_vjp",
     "nf_multipoles",
     "nf_step_stats",
@@ -87,6 +89,9 @@ def load():
     lib.nf_accel.restype = ctypes.c_int
     lib.nf_accel.argtypes = [ctypes.c_int, P, ctypes.c_double, ctypes.c_uint32,
                              ctypes.POINTER(vp), vp, ctypes.c_size_t, vp]
+    lib.nf_accel_noalloc.restype = ctypes.c_int
+    lib.nf_accel_noalloc.argtypes = [ctypes.c_int, P, ctypes.c_double, ctypes.c_uint32,
+                                     ctypes.POINTER(vp), vp]
     lib.nf_accel_vjp.restype = ctypes.c_int
     lib.nf_accel_vjp.argtypes = [ctypes.c_int, P, ctypes.c_double, ctypes.c_uint32,
                                  ctypes.POINTER(vp), ctypes.POINTER(vp), vp, ctypes.c_size_t, vp]

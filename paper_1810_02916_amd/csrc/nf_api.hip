@@ -94,6 +94,7 @@ struct Layout {
     size_t mp_npieces_off = 0, mp_scan_off = 0, mp_pieces_off = 0, mp_partial_off = 0;
     int64_t mp_max_pieces = 0;
     int64_t max_dense = 0;
+    size_t accel_end = 0;   // bytes an accelerations call uses (table + planner)
     size_t total = 0;
     int64_t nblk = 0;
     int passes = 0;
@@ -162,10 +163,9 @@ int validate(int nbox, const nf_box *boxes, Layout &L) {
         std::max(scan_scratch_words((int64_t)kRadix * L.nblk), scan_scratch_words(L.C + 1));
     o = align_up(o + 4 * (size_t)scan_words, 256);
     const size_t bin_end = o;
-    // force scratch reuses the binning scratch region
+    // force scratch reuses the binning scratch region: the planner's tables
+    // first, then the VJP's source records
     o = scratch0;
-    L.cot_off = o;   // VJP source records: 32 bytes per particle
-    o = align_up(o + 32 * (size_t)L.N, 256);
     L.cellinfo_off = o;
     o = align_up(o + 4 * (size_t)L.C, 256);
     L.bucket_off = o;
@@ -180,6 +180,9 @@ int validate(int nbox, const nf_box *boxes, Layout &L) {
     o = align_up(o + sizeof(Item) * (size_t)(L.C + 16), 256);
     L.counter_off = o;
     o = align_up(o + 4 * (size_t)queue_words(), 256);
+    L.accel_end = o;
+    L.cot_off = o;   // VJP source records: 32 bytes per particle
+    o = align_up(o + 32 * (size_t)L.N, 256);
     const size_t force_end = o;
     // step-statistics scratch, also over the binning scratch region
     o = scratch0;
@@ -250,6 +253,46 @@ void fill_geometry(const nf_box &B, const Layout &L, int b, DevBox &d, bool plum
     d.cell_start = B.cell_start;
     d.order = B.order;
     d.nbad = B.nbad;
+}
+
+}  // namespace
+}  // namespace nf
+
+// Scratch of the allocation-free accelerations (nf_accel_noalloc): one array
+// per GPU, held from the library's load on that GPU until the process ends.
+// Host code never uses the name `scratch` as an address (on the host it is a
+// stand-in, not device memory): every use goes through the device address
+// that hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[NF_NOALLOC_SCRATCH_BYTES];
+
+namespace nf {
+namespace {
+
+std::mutex g_scratch_mu;
+std::vector<void *> g_scratch_ptr;   // per device: device address of `scratch`
+
+// Device address of the current device's `scratch`, looked up once per device
+// (with that device current) and kept.
+int static_scratch(void *&ptr, std::string &why) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        why = std::string("hipGetDevice: ") + hipGetErrorString(e);
+        return NF_EHIP;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            why = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+            return NF_EHIP;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    ptr = g_scratch_ptr[dev];
+    return NF_OK;
 }
 
 }  // namespace
@@ -327,9 +370,13 @@ int nf_bin_particles(int nbox, const nf_box *boxes, void *ws, size_t ws_bytes, v
     }
 }
 
+
+// noalloc: the workspace is the static `scratch` array of the current device
+// (ws and ws_bytes are ignored), and the force kernels run one after another
+// on the caller's stream (no library side streams or events).
 static int force_common(int nbox, const nf_box *boxes, double gm, uint32_t flags,
                         const float *const *cot, float *const *out, void *ws, size_t ws_bytes,
-                        void *stream, bool vjp) {
+                        void *stream, bool vjp, bool noalloc = false) {
     Layout L;
     int rc = validate(nbox, boxes, L);
     if (rc) return rc;
@@ -342,9 +389,24 @@ static int force_common(int nbox, const nf_box *boxes, double gm, uint32_t flags
         if (boxes[b].n > 0 && !out[b]) return fail(NF_EINVAL, "output pointer is NULL");
         if (vjp && boxes[b].n > 0 && !cot[b]) return fail(NF_EINVAL, "cotangent pointer is NULL");
     }
-    if ((rc = check_ws(L, ws, ws_bytes))) return rc;
     std::string why;
-    if ((rc = check_device(why))) return fail(rc, why);
+    if (noalloc) {
+        if (vjp) return fail(NF_EINVAL, "internal error");
+        if (L.accel_end > (size_t)NF_NOALLOC_SCRATCH_BYTES) {
+            char m[160];
+            std::snprintf(m, sizeof m,
+                          "the call needs %zu bytes of scratch; the allocation-free entry point "
+                          "holds %zu",
+                          L.accel_end, (size_t)NF_NOALLOC_SCRATCH_BYTES);
+            return fail(NF_EUNSUPPORTED, m);
+        }
+        if ((rc = check_device(why))) return fail(rc, why);
+        if ((rc = static_scratch(ws, why))) return fail(rc, why);
+        ws_bytes = NF_NOALLOC_SCRATCH_BYTES;
+    } else {
+        if ((rc = check_ws(L, ws, ws_bytes))) return rc;
+        if ((rc = check_device(why))) return fail(rc, why);
+    }
     std::vector<DevBox> tab((size_t)nbox);
     for (int b = 0; b < nbox; ++b) {
         fill_geometry(boxes[b], L, b, tab[b], (flags & NF_PLUMMER) != 0,
@@ -381,7 +443,7 @@ static int force_common(int nbox, const nf_box *boxes, double gm, uint32_t flags
         e = vjp ? gather_cot_launch(d_tab, nbox, p, s) : hipSuccess;
         if (e == hipSuccess) e = plan_launch(d_tab, nbox, tp, s);
         if (e == hipSuccess)
-            e = tile_launch(d_tab, vjp ? 1 : 0, p.compensated, tp, p.cot_sorted, s);
+            e = tile_launch(d_tab, vjp ? 1 : 0, p.compensated, tp, p.cot_sorted, !noalloc, s);
     }
     if (e != hipSuccess) return fail(NF_EHIP, std::string("force launch: ") + hipGetErrorString(e));
     g_last_error.clear();
@@ -392,6 +454,16 @@ int nf_accel(int nbox, const nf_box *boxes, double gm, uint32_t flags, float *co
              void *ws, size_t ws_bytes, void *stream) {
     try {
         return force_common(nbox, boxes, gm, flags, nullptr, acc, ws, ws_bytes, stream, false);
+    } catch (...) {
+        return fail(NF_EINVAL, "internal error");
+    }
+}
+
+int nf_accel_noalloc(int nbox, const nf_box *boxes, double gm, uint32_t flags,
+                     float *const *acc, void *stream) {
+    try {
+        return force_common(nbox, boxes, gm, flags, nullptr, acc, nullptr, 0, stream, false,
+                            true);
     } catch (...) {
         return fail(NF_EINVAL, "internal error");
     }

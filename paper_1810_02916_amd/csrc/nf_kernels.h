@@ -44,9 +44,11 @@ struct TilePlan {
 int plan_buckets();
 int queue_words();
 hipError_t plan_launch(const DevBox *d_boxes, int nbox, const TilePlan &tp, hipStream_t s);
-// mode 0: accelerations, 1: VJP (cot = cotangents in sorted order)
+// mode 0: accelerations, 1: VJP (cot = cotangents in sorted order).
+// concurrent: the light and narrow kernels run on the library's side streams
+// alongside the dense kernel; otherwise all three run in turn on s.
 hipError_t tile_launch(const DevBox *d_boxes, int mode, bool compensated, const TilePlan &tp,
-                       const float4 *cot, hipStream_t s);
+                       const float4 *cot, bool concurrent, hipStream_t s);
 
 // Per-cell multipole moments (nf_multipole.hip).
 int multipole_max_order();

@@ -860,7 +860,7 @@ hipError_t side_stream(SideStream &out) {   // caller holds g_side_mu
 
 template <int MODE, bool COMP>
 hipError_t launch_force(const DevBox *d_boxes, const TilePlan &tp, const float4 *cot,
-                        hipStream_t s) {
+                        bool concurrent, hipStream_t s) {
     constexpr int CAP = MODE == 0 ? 1024 : 768;
     constexpr int NCAP = MODE == 0 ? 256 : 192;   // narrow items: 4 KB windows (4.5 KB, VJP)
     static const int gd = persistent_grid(k_dense<MODE, COMP>, kUnit);
@@ -871,6 +871,21 @@ hipError_t launch_force(const DevBox *d_boxes, const TilePlan &tp, const float4 
     static const int gn =
         (persistent_grid(k_light<MODE, COMP, NCAP, kNarrowThreads>, kNarrowThreads) + kQueues -
          1) / kQueues * kQueues;
+    if (!concurrent) {   // the three kernels in turn on the caller's stream
+        hipLaunchKernelGGL((k_light<MODE, COMP, CAP, kLightThreads>), dim3(gl),
+                           dim3(kLightThreads), 0, s, d_boxes, (const Item *)tp.light,
+                           (const uint32_t *)tp.totals, tp.counter + kQueueStride, cot, 1);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_light<MODE, COMP, NCAP, kNarrowThreads>), dim3(gn),
+                           dim3(kNarrowThreads), 0, s, d_boxes, (const Item *)tp.light,
+                           (const uint32_t *)tp.totals, tp.counter + kQueueStride * (1 + kQueues),
+                           cot, 2);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL((k_dense<MODE, COMP>), dim3(gd), dim3(kUnit), 0, s, d_boxes,
+                           (const Item *)tp.dense, (const uint32_t *)tp.totals, tp.counter, cot);
+        return hipGetLastError();
+    }
     std::lock_guard<std::mutex> lk(g_side_mu);
     SideStream ss;
     hipError_t e = side_stream(ss);
@@ -918,14 +933,14 @@ hipError_t plan_launch(const DevBox *d_boxes, int nbox, const TilePlan &tp, hipS
 }
 
 hipError_t tile_launch(const DevBox *d_boxes, int mode, bool compensated, const TilePlan &tp,
-                       const float4 *cot, hipStream_t s) {
+                       const float4 *cot, bool concurrent, hipStream_t s) {
     hipError_t e = fill_u32(tp.counter, queue_words(), 0u, s);
     if (e != hipSuccess) return e;
     if (mode == 0)
-        return compensated ? launch_force<0, true>(d_boxes, tp, cot, s)
-                           : launch_force<0, false>(d_boxes, tp, cot, s);
-    return compensated ? launch_force<1, true>(d_boxes, tp, cot, s)
-                       : launch_force<1, false>(d_boxes, tp, cot, s);
+        return compensated ? launch_force<0, true>(d_boxes, tp, cot, concurrent, s)
+                           : launch_force<0, false>(d_boxes, tp, cot, concurrent, s);
+    return compensated ? launch_force<1, true>(d_boxes, tp, cot, concurrent, s)
+                       : launch_force<1, false>(d_boxes, tp, cot, concurrent, s);
 }
 
 }  // namespace nf

@@ -28,6 +28,7 @@ __all__ = [
     "bin_particles_batched",
     "rebin",
     "accel",
+    "accel_noalloc",
     "accel_vjp",
     "multipole_terms",
     "step_stats",
@@ -210,6 +211,23 @@ def accel(b: Binned, gm: float = 1.0, *, compensated: bool = False, simple: bool
                           _flags(compensated, simple, plummer, spline_everywhere), ptrs,
                           ctypes.c_void_p(b.workspace.data_ptr()), b.workspace.numel(),
                           _stream_handle(b.device))
+    _lib.check(rc)
+    return out[0] if b.nbox == 1 else out
+
+
+def accel_noalloc(b: Binned, gm: float = 1.0, *, compensated: bool = False,
+                  simple: bool = False, plummer: bool = False,
+                  spline_everywhere: bool = False, out: Optional[List[torch.Tensor]] = None):
+    """``accel`` through the allocation-free entry point (nf_accel_noalloc):
+    the library's static per-GPU scratch instead of the boxes' workspace.
+    With ``out`` given, the call itself allocates nothing."""
+    lib = _lib.load()
+    if out is None:
+        out = [torch.empty((bx.n, 3), dtype=torch.float32, device=b.device) for bx in b.boxes]
+    with torch.cuda.device(b.device):
+        rc = lib.nf_accel_noalloc(b.nbox, b.carray(), float(gm),
+                                  _flags(compensated, simple, plummer, spline_everywhere),
+                                  _ptr_array(out), _stream_handle(b.device))
     _lib.check(rc)
     return out[0] if b.nbox == 1 else out
 

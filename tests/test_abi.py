@@ -170,3 +170,20 @@ def test_size_limits_of_the_32bit_index_range(lib):
     outs = (ctypes.c_void_p * 1)(0x2000)
     assert L.nf_accel(1, over, 1.0, 0, outs, ctypes.c_void_p(0x100000), 1 << 20,
                       None) == lib.NF_EUNSUPPORTED
+
+
+def test_noalloc_rejects_without_a_device(lib):
+    """nf_accel_noalloc validates like nf_accel and refuses, on the host, a
+    call whose scratch exceeds its static array (160^3 cells need ~80 MiB)."""
+    L = lib.load()
+    outs = (ctypes.c_void_p * 1)(0x2000)
+    big = (lib.NfBox * 1)(_box(lib, 10, K=160))
+    assert L.nf_accel_noalloc(1, big, 1.0, 0, outs, None) == lib.NF_EUNSUPPORTED
+    assert "scratch" in lib.last_error()
+    good = (lib.NfBox * 1)(_box(lib, 10))
+    assert L.nf_accel_noalloc(1, good, 1.0, 1 << 7, outs, None) == lib.NF_EINVAL
+    nulls = (ctypes.c_void_p * 1)(None)
+    assert L.nf_accel_noalloc(1, good, 1.0, 0, nulls, None) == lib.NF_EINVAL
+    assert L.nf_accel_noalloc(1, (lib.NfBox * 1)(_box(lib, 10, K=4)), 1.0, 0, outs,
+                              None) == lib.NF_EINVAL
+    assert lib.NF_NOALLOC_SCRATCH_BYTES == 32 << 20
