@@ -129,11 +129,12 @@ def bench_batched(args):
     Ks, Ls, Es = [s.K for s in specs], [s.L for s in specs], [s.eps_s for s in specs]
 
     def per_box():
-        return [nfp.accel(nfp.bin_particles(p, K, L, e), 1.0, compensated=True)
+        return [nfp.accel(nfp.bin_particles(p, K, L, e, check=False), 1.0, compensated=True)
                 for p, K, L, e in zip(pos, Ks, Ls, Es)]
 
     def batched():
-        return nfp.accel(nfp.bin_particles_batched(pos, Ks, Ls, Es), 1.0, compensated=True)
+        return nfp.accel(nfp.bin_particles_batched(pos, Ks, Ls, Es, check=False), 1.0,
+                         compensated=True)
 
     cf = nfp.CapturedForce(pos, Ks, Ls, Es, 1.0, compensated=True)
 
@@ -205,7 +206,7 @@ def main():
     def step(ev=None):
         if ev is not None:
             ev[0].record(stream)
-        b = nfp.bin_particles(pos, sp.K, sp.L, sp.eps_s)
+        b = nfp.bin_particles(pos, sp.K, sp.L, sp.eps_s, check=False)
         if ev is not None:
             ev[1].record(stream)
         a0 = nfp.accel(b, 1.0)

@@ -240,11 +240,34 @@ int nf_multipoles(int nbox, const nf_box *boxes, int order, float *const *mom, v
  *   glob[3 b + 0..2] = (max_i |a_i|, sqrt(mean_i |v_i|^2), max_i |v_i|)
  *     (device double array of 3 nbox values).
  * Double precision inside, fixed summation order (bitwise reproducible).
- * The step itself is a host computation on these values.
+ * nf_step_choose turns these values into the step.
  */
 int nf_step_stats(int nbox, const nf_box *boxes, const float *const *acc,
                   const float *const *vel, float *const *amax, float *const *vrms,
                   double *glob, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * The global step of Sec. 4.2 from the outputs of nf_step_stats (amax, vrms:
+ * nbox device pointers to [K_b^3] float; glob: device [nbox][3] double).
+ * The section bounds the one step of all particles by a largest step in ln a,
+ * by eta times the ratio v_rms / a_max evaluated within each cell, with the
+ * box-wide ratio as a floor against cold cells, and by the step in which the
+ * fastest particle moves 80% of a cell.  Per box b, into the device array
+ * bounds [nbox][4] double:
+ *   bounds[4b+0] = dlna_max / hubble
+ *   bounds[4b+1] = eta * max(min over cells with amax > 0 of vrms / amax,
+ *                            glob[3b+1] / glob[3b+0])
+ *   bounds[4b+2] = (0.8 * L / K) / glob[3b+2]
+ *   bounds[4b+3] = the smallest of the three (the step)
+ * Each ratio is one double division of the stored values (the per-cell floats
+ * widened to double); a ratio whose denominator is zero is +inf; no
+ * multiply-add is fused, so the values are bitwise reproducible.  dlna_max,
+ * hubble and eta must be finite and > 0 (hubble is the caller's H, giving
+ * the ln a bound in time units).
+ */
+int nf_step_choose(int nbox, const nf_box *boxes, const float *const *amax,
+                   const float *const *vrms, const double *glob, double dlna_max, double hubble,
+                   double eta, double *bounds, void *ws, size_t ws_bytes, void *stream);
 
 /*
  * The step's Kick and Drift stages, kick then drift, in caller order:

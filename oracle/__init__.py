@@ -18,4 +18,4 @@ from .oracle import (  # noqa: F401
 )
 from .brute import brute_accel  # noqa: F401
 from .multipoles import abs_moments, multipoles, terms  # noqa: F401
-from .stepping import choose_step, kick_drift, step_stats  # noqa: F401
+from .stepping import choose_step, kick_drift, step_bounds, step_stats  # noqa: F401

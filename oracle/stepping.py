@@ -54,13 +54,25 @@ def step_stats(pos, K: int, L: float, acc, vel):
     return amax, vrms, glob
 
 
-def choose_step(amax, vrms, glob, *, dlna_max: float, hubble: float, eta: float,
-                cell_width: float) -> float:
-    """The smallest of the three bounds of Sec. 4.2 (time units of 1/hubble)."""
+def step_bounds(amax, vrms, glob, *, dlna_max: float, hubble: float, eta: float,
+                cell_width: float):
+    """The three bounds of Sec. 4.2 (time units of 1/hubble): the largest
+    step in ln a, eta times the per-cell ratio (raised to the global ratio
+    when that is larger), and 80% of a cell at the fastest particle's speed;
+    +inf for a ratio whose denominator is zero."""
+    amax = np.asarray(amax, dtype=np.float64)
+    vrms = np.asarray(vrms, dtype=np.float64)
     dt1 = dlna_max / hubble
     ok = amax > 0
     cell_ratio = float(np.min(vrms[ok] / amax[ok])) if ok.any() else np.inf
     glob_ratio = glob[1] / glob[0] if glob[0] > 0 else np.inf
     dt2 = eta * max(cell_ratio, glob_ratio)
     dt3 = 0.8 * cell_width / glob[2] if glob[2] > 0 else np.inf
-    return float(min(dt1, dt2, dt3))
+    return float(dt1), float(dt2), float(dt3)
+
+
+def choose_step(amax, vrms, glob, *, dlna_max: float, hubble: float, eta: float,
+                cell_width: float) -> float:
+    """The smallest of the three bounds of Sec. 4.2."""
+    return min(step_bounds(amax, vrms, glob, dlna_max=dlna_max, hubble=hubble, eta=eta,
+                           cell_width=cell_width))

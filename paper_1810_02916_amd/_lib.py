@@ -37,6 +37,7 @@ EXPORTED = (
     "nf_accel_vjp",
     "nf_multipoles",
     "nf_step_stats",
+    "nf_step_choose",
     "nf_kick_drift",
 )
 
@@ -98,6 +99,9 @@ def load():
     PP = ctypes.POINTER(vp)
     lib.nf_step_stats.restype = ctypes.c_int
     lib.nf_step_stats.argtypes = [ctypes.c_int, P, PP, PP, PP, PP, vp, vp, ctypes.c_size_t, vp]
+    lib.nf_step_choose.restype = ctypes.c_int
+    lib.nf_step_choose.argtypes = [ctypes.c_int, P, PP, PP, vp, ctypes.c_double, ctypes.c_double,
+                                   ctypes.c_double, vp, vp, ctypes.c_size_t, vp]
     lib.nf_kick_drift.restype = ctypes.c_int
     lib.nf_kick_drift.argtypes = [ctypes.c_int, P, PP, PP, PP, ctypes.c_double, ctypes.c_double,
                                   vp, ctypes.c_size_t, vp]

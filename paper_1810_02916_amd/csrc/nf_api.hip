@@ -239,6 +239,7 @@ void fill_geometry(const nf_box &B, const Layout &L, int b, DevBox &d, bool plum
     d.base = L.base[b];
     d.cellbase = L.cellbase[b];
     d.kappa = (double)B.K / B.L;
+    d.cellw = B.L / (double)B.K;
     const double eps = B.eps_s * d.kappa;
     d.eps = (float)eps;
     d.cA = (float)(10.0 / (eps * eps * eps));
@@ -513,7 +514,7 @@ int nf_step_stats(int nbox, const nf_box *boxes, const float *const *acc,
             if (boxes[b].n > 0 && (!acc[b] || !vel[b]))
                 return fail(NF_EINVAL, "acc/vel pointer is NULL");
             if (!amax[b] || !vrms[b]) return fail(NF_EINVAL, "amax/vrms pointer is NULL");
-            io[b] = StepIO{acc[b], vel[b], nullptr, nullptr, amax[b], vrms[b]};
+            io[b] = StepIO{acc[b], vel[b], nullptr, nullptr, amax[b], vrms[b], nullptr, nullptr};
         }
         hipStream_t s = static_cast<hipStream_t>(stream);
         DevBox *d_tab = nullptr;
@@ -524,6 +525,40 @@ int nf_step_stats(int nbox, const nf_box *boxes, const float *const *acc,
                                          reinterpret_cast<CellStat *>(w + L.cellstat_off),
                                          reinterpret_cast<CellStat *>(w + L.partial_off), glob, s);
         if (e != hipSuccess) return fail(NF_EHIP, std::string("step stats: ") + hipGetErrorString(e));
+        g_last_error.clear();
+        return NF_OK;
+    } catch (...) {
+        return fail(NF_EINVAL, "internal error");
+    }
+}
+
+int nf_step_choose(int nbox, const nf_box *boxes, const float *const *amax,
+                   const float *const *vrms, const double *glob, double dlna_max, double hubble,
+                   double eta, double *bounds, void *ws, size_t ws_bytes, void *stream) {
+    try {
+        Layout L;
+        int rc = validate(nbox, boxes, L);
+        if (rc) return rc;
+        if (!amax || !vrms || !glob || !bounds)
+            return fail(NF_EINVAL, "amax, vrms, glob and bounds must not be NULL");
+        if (!(dlna_max > 0) || !std::isfinite(dlna_max) || !(hubble > 0) ||
+            !std::isfinite(hubble) || !(eta > 0) || !std::isfinite(eta))
+            return fail(NF_EINVAL, "dlna_max, hubble and eta must be finite and > 0");
+        std::vector<StepIO> io((size_t)nbox);
+        for (int b = 0; b < nbox; ++b) {
+            if (!amax[b] || !vrms[b]) return fail(NF_EINVAL, "amax/vrms pointer is NULL");
+            io[b] = StepIO{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, amax[b], vrms[b]};
+        }
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        DevBox *d_tab = nullptr;
+        StepIO *d_io = nullptr;
+        if ((rc = step_common(nbox, boxes, io, ws, ws_bytes, s, L, d_tab, d_io))) return rc;
+        char *w = static_cast<char *>(ws);
+        const StepChoice ch{dlna_max, hubble, eta};
+        hipError_t e = step_choose_launch(d_tab, d_io, nbox,
+                                          reinterpret_cast<double *>(w + L.partial_off), glob, ch,
+                                          bounds, s);
+        if (e != hipSuccess) return fail(NF_EHIP, std::string("step choice: ") + hipGetErrorString(e));
         g_last_error.clear();
         return NF_OK;
     } catch (...) {
@@ -545,7 +580,7 @@ int nf_kick_drift(int nbox, const nf_box *boxes, const float *const *acc, float 
         for (int b = 0; b < nbox; ++b) {
             if (boxes[b].n > 0 && (!acc[b] || !vel[b] || !pos[b]))
                 return fail(NF_EINVAL, "acc/vel/pos pointer is NULL");
-            io[b] = StepIO{acc[b], nullptr, vel[b], pos[b], nullptr, nullptr};
+            io[b] = StepIO{acc[b], nullptr, vel[b], pos[b], nullptr, nullptr, nullptr, nullptr};
         }
         hipStream_t s = static_cast<hipStream_t>(stream);
         DevBox *d_tab = nullptr;

@@ -47,6 +47,7 @@ struct DevBox {
     int64_t base;         // first element of this box in the concatenated arrays
     int64_t cellbase;     // first key of this box in the concatenated key space
     double kappa;         // K / L (cells per length unit), double
+    double cellw;         // L / K (cell width in length units), double
     float eps;            // spline radius in cell widths (eps_s * kappa)
     float scale;          // gm * kappa^2 (accel) or gm * kappa^3 (vjp)
     float cA, cB, cC;     // Eq. 2 in cell widths: F/r = cA + cB r + cC r^2 inside eps

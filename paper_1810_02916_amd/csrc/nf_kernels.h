@@ -85,6 +85,10 @@ struct StepIO {                 // per box, caller order
     float *vel_rw;              // [n][3] (kick)
     double *pos_rw;             // [n][3] (drift)
     float *amax, *vrms;         // [K^3] per-cell outputs
+    const float *amax_in, *vrms_in;   // [K^3] per-cell inputs of the step choice
+};
+struct StepChoice {             // the caller's constants of the step choice
+    double dlna_max, hubble, eta;
 };
 struct CellStat {               // per cell: max |a|, sum |v|^2, max |v|^2
     double amax, v2sum, vmax2;
@@ -93,6 +97,9 @@ constexpr int kStepBlocks = 256;   // partial reductions per box (power of two)
 hipError_t step_stats_launch(const DevBox *d_boxes, const StepIO *d_io, int nbox,
                              int64_t max_ncell, CellStat *scratch, CellStat *partial,
                              double *glob, hipStream_t s);
+hipError_t step_choose_launch(const DevBox *d_boxes, const StepIO *d_io, int nbox,
+                              double *partial, const double *glob, const StepChoice &ch,
+                              double *bounds, hipStream_t s);
 hipError_t kick_drift_launch(const DevBox *d_boxes, const StepIO *d_io, int nbox, int64_t max_n,
                              double kick, double drift, hipStream_t s);
 

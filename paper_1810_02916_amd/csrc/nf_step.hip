@@ -9,6 +9,9 @@
 //                  cell's (a_max, sum |v|^2, max |v|^2) in double scratch;
 //   k_step_partial fixed cell ranges per block -> per-block partials;
 //   k_step_final   one block per box -> (a_max, v_rms, v_max) in double.
+//   k_choose_partial, k_choose_final
+//                  the step itself: the smallest per-cell ratio, then the
+//                  three bounds and their minimum, per box.
 //   k_kick_drift   v <- v + kick * a (double, rounded once to float),
 //                  x <- x + drift * v (double, kicked v), caller order.
 // Every sum has a fixed order (lane-strided, then a fixed butterfly or
@@ -129,6 +132,68 @@ k_step_final(const DevBox *__restrict__ boxes, const CellStat *__restrict__ part
     }
 }
 
+// Step choice, stage 1: block b of box y takes the smallest v_rms / a_max
+// over the cells of its fixed range whose a_max is positive (+inf if none),
+// each ratio one double division of the stored float values.
+__global__ void __launch_bounds__(kStatThreads)
+k_choose_partial(const DevBox *__restrict__ boxes, const StepIO *__restrict__ io,
+                 double *__restrict__ partial) {
+    __shared__ double red[kStatThreads];
+    const DevBox &B = boxes[blockIdx.y];
+    const StepIO &S = io[blockIdx.y];
+    const int t = threadIdx.x;
+    const int chunk = (B.ncell + kStepBlocks - 1) / kStepBlocks;
+    const int c0 = blockIdx.x * chunk, c1 = min(B.ncell, c0 + chunk);
+    double r = __longlong_as_double(0x7ff0000000000000ll);   // +inf
+    for (int c = c0 + t; c < c1; c += kStatThreads) {
+        const float am = S.amax_in[c];
+        if (am > 0.0f) r = fmin(r, __ddiv_rn((double)S.vrms_in[c], (double)am));
+    }
+    red[t] = r;
+    __syncthreads();
+    for (int h = kStatThreads / 2; h >= 1; h >>= 1) {
+        if (t < h) red[t] = fmin(red[t], red[t + h]);
+        __syncthreads();
+    }
+    if (t == 0) partial[(int64_t)blockIdx.y * kStepBlocks + blockIdx.x] = red[0];
+}
+
+// Step choice, stage 2 (Sec. 4.2), one block per box: the cell ratio is the
+// smallest partial; then
+//   b0 = dlna_max / hubble                       (largest step in ln a)
+//   b1 = eta * max(cell ratio, v_rms / a_max)    (the global ratio protects
+//                                                  against cold cells)
+//   b2 = (0.8 * cell width) / v_max              (80% of a cell)
+//   b3 = min(b0, b1, b2)
+// with +inf for a ratio whose denominator is zero.
+__global__ void __launch_bounds__(kStepBlocks)
+k_choose_final(const DevBox *__restrict__ boxes, const double *__restrict__ partial,
+               const double *__restrict__ glob, StepChoice ch, double *__restrict__ bounds) {
+#pragma clang fp contract(off)
+    __shared__ double red[kStepBlocks];
+    const DevBox &B = boxes[blockIdx.x];
+    const int t = threadIdx.x;
+    red[t] = partial[(int64_t)blockIdx.x * kStepBlocks + t];
+    __syncthreads();
+    for (int h = kStepBlocks / 2; h >= 1; h >>= 1) {
+        if (t < h) red[t] = fmin(red[t], red[t + h]);
+        __syncthreads();
+    }
+    if (t == 0) {
+        const double inf = __longlong_as_double(0x7ff0000000000000ll);
+        const double *g = glob + 3 * (int64_t)blockIdx.x;
+        const double gratio = g[0] > 0.0 ? __ddiv_rn(g[1], g[0]) : inf;
+        const double b0 = __ddiv_rn(ch.dlna_max, ch.hubble);
+        const double b1 = ch.eta * fmax(red[0], gratio);
+        const double b2 = g[2] > 0.0 ? __ddiv_rn(0.8 * B.cellw, g[2]) : inf;
+        double *o = bounds + 4 * (int64_t)blockIdx.x;
+        o[0] = b0;
+        o[1] = b1;
+        o[2] = b2;
+        o[3] = fmin(fmin(b0, b1), b2);
+    }
+}
+
 __global__ void __launch_bounds__(256)
 k_kick_drift(const DevBox *__restrict__ boxes, const StepIO *__restrict__ io, double kick,
              double drift) {
@@ -164,6 +229,18 @@ hipError_t step_stats_launch(const DevBox *d_boxes, const StepIO *d_io, int nbox
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_step_final, dim3((unsigned)nbox), dim3(kStepBlocks), 0, s, d_boxes,
                        (const CellStat *)partial, glob);
+    return hipGetLastError();
+}
+
+hipError_t step_choose_launch(const DevBox *d_boxes, const StepIO *d_io, int nbox,
+                              double *partial, const double *glob, const StepChoice &ch,
+                              double *bounds, hipStream_t s) {
+    hipLaunchKernelGGL(k_choose_partial, dim3(kStepBlocks, (unsigned)nbox), dim3(kStatThreads), 0,
+                       s, d_boxes, d_io, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_choose_final, dim3((unsigned)nbox), dim3(kStepBlocks), 0, s, d_boxes,
+                       (const double *)partial, glob, ch, bounds);
     return hipGetLastError();
 }
 

@@ -33,6 +33,7 @@ __all__ = [
     "multipole_terms",
     "step_stats",
     "kick_drift",
+    "step_bounds",
     "choose_step",
     "multipoles",
     "NearFieldAccel",
@@ -134,11 +135,21 @@ def _alloc_box(pos: torch.Tensor, K: int, L: float, eps_s: float) -> _BoxBuffers
     )
 
 
+def _check_nbad(b: Binned) -> None:
+    bad = b.nbad()
+    if any(bad):
+        raise ValueError(f"non-finite or out-of-range positions: {bad} per box (such particles "
+                         "are binned into cell 0 and every force of their box is meaningless)")
+
+
 def bin_particles_batched(positions: Sequence[torch.Tensor], Ks: Sequence[int],
                           Ls: Sequence[float], eps: Sequence[float],
-                          dense_min: int = 0) -> Binned:
+                          dense_min: int = 0, check: bool = True) -> Binned:
     """Bin several boxes in one call (one radix sort over all of them).
-    ``dense_min`` is the force kernels' tile choice (0: library default)."""
+    ``dense_min`` is the force kernels' tile choice (0: library default).
+    ``check``: read back the library's count of non-finite positions and raise
+    ValueError if any box has one (one device synchronisation; pass False to
+    skip it and inspect ``Binned.nbad()`` yourself)."""
     lib = _lib.load()
     if not (len(positions) == len(Ks) == len(Ls) == len(eps)) or len(positions) == 0:
         raise ValueError("positions, Ks, Ls and eps must be non-empty and of equal length")
@@ -162,23 +173,28 @@ def bin_particles_batched(positions: Sequence[torch.Tensor], Ks: Sequence[int],
     _lib.check(rc)
     out = Binned(boxes=boxes, workspace=ws, device=dev)
     out._arr = arr
+    if check:
+        _check_nbad(out)
     return out
 
 
-def rebin(b: Binned) -> Binned:
-    """Bin again into the same buffers (positions updated in place)."""
+def rebin(b: Binned, check: bool = True) -> Binned:
+    """Bin again into the same buffers (positions updated in place);
+    ``check`` as in ``bin_particles_batched``."""
     lib = _lib.load()
     with torch.cuda.device(b.device):
         rc = lib.nf_bin_particles(b.nbox, b.carray(), ctypes.c_void_p(b.workspace.data_ptr()),
                                   b.workspace.numel(), _stream_handle(b.device))
     _lib.check(rc)
+    if check:
+        _check_nbad(b)
     return b
 
 
 def bin_particles(pos: torch.Tensor, K: int, L: float, eps_s: float,
-                  dense_min: int = 0) -> Binned:
+                  dense_min: int = 0, check: bool = True) -> Binned:
     """Bin one box: cell offsets (FP64 -> FP32) and a stable sort by cell."""
-    return bin_particles_batched([pos], [K], [L], [eps_s], dense_min)
+    return bin_particles_batched([pos], [K], [L], [eps_s], dense_min, check)
 
 
 def _flags(compensated: bool, simple: bool, plummer: bool = False,
@@ -327,20 +343,42 @@ def kick_drift(b: Binned, acc, vel, pos, kick: float, drift: float) -> None:
     _lib.check(rc)
 
 
-def choose_step(amax, vrms, glob, *, dlna_max: float, hubble: float, eta: float,
-                cell_width: float) -> float:
-    """The step of Sec. 4.2 from one box's statistics: the smallest of
-    dlna_max / hubble, eta * max(global v_rms / a_max, smallest per-cell
-    v_rms / a_max over cells with a_max > 0), and 0.8 cell_width / v_max."""
-    am = amax.double()
-    ok = am > 0
-    cell_ratio = float((vrms.double()[ok] / am[ok]).min()) if bool(ok.any()) else float("inf")
-    g = [float(x) for x in glob]
-    glob_ratio = g[1] / g[0] if g[0] > 0 else float("inf")
-    dt1 = dlna_max / hubble
-    dt2 = eta * max(cell_ratio, glob_ratio)
-    dt3 = 0.8 * cell_width / g[2] if g[2] > 0 else float("inf")
-    return min(dt1, dt2, dt3)
+def step_bounds(b: Binned, amax, vrms, glob, *, dlna_max: float, hubble: float,
+                eta: float) -> torch.Tensor:
+    """The three step bounds of Sec. 4.2 and the step, per box, from
+    ``step_stats`` output, computed by the library (nf_step_choose): float64
+    [nbox, 4] on the device = (dlna_max / hubble, eta * max(smallest per-cell
+    v_rms / a_max, global v_rms / a_max), 0.8 cell width / v_max, step)."""
+    lib = _lib.load()
+    am = [amax] if isinstance(amax, torch.Tensor) else list(amax)
+    vr = [vrms] if isinstance(vrms, torch.Tensor) else list(vrms)
+    if len(am) != b.nbox or len(vr) != b.nbox:
+        raise ValueError("one amax and one vrms tensor per box is required")
+    for x, bx in zip(am + vr, b.boxes + b.boxes):
+        if x.dtype != torch.float32 or not x.is_contiguous() or x.numel() != bx.K ** 3 \
+                or x.device != b.device:
+            raise ValueError("amax and vrms must be contiguous float32 [K^3] tensors on the "
+                             "boxes' device")
+    g = glob.reshape(-1, 3)
+    if g.dtype != torch.float64 or not g.is_contiguous() or g.shape[0] != b.nbox \
+            or g.device != b.device:
+        raise ValueError("glob must be a contiguous float64 [nbox, 3] tensor on the boxes' device")
+    out = torch.empty((b.nbox, 4), dtype=torch.float64, device=b.device)
+    with torch.cuda.device(b.device):
+        rc = lib.nf_step_choose(b.nbox, b.carray(), _ptr_array(am), _ptr_array(vr),
+                                ctypes.c_void_p(g.data_ptr()), float(dlna_max), float(hubble),
+                                float(eta), ctypes.c_void_p(out.data_ptr()),
+                                ctypes.c_void_p(b.workspace.data_ptr()), b.workspace.numel(),
+                                _stream_handle(b.device))
+    _lib.check(rc)
+    return out
+
+
+def choose_step(b: Binned, amax, vrms, glob, *, dlna_max: float, hubble: float,
+                eta: float) -> float:
+    """The step of Sec. 4.2 for one box (``step_bounds``' last column)."""
+    return float(step_bounds(b, amax, vrms, glob, dlna_max=dlna_max, hubble=hubble,
+                             eta=eta)[0, 3])
 
 
 class NearFieldAccel(torch.autograd.Function):
@@ -380,7 +418,9 @@ class CapturedForce:
 
     Every library call is a pure sequence of kernel launches (descriptors go
     through kernel arguments, buffers are filled by kernels), so the whole
-    step is one graph launch."""
+    step is one graph launch.  A replay cannot stop on bad input: check
+    ``nbad()`` (the binning's count of non-finite positions per box, as of
+    the last replay) before trusting its forces."""
 
     def __init__(self, positions: Sequence[torch.Tensor], Ks, Ls, eps, gm: float = 1.0,
                  compensated: bool = False, plummer: bool = False):
@@ -396,10 +436,15 @@ class CapturedForce:
         torch.cuda.synchronize(self.binned.device)
         self.graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(self.graph):
-            rebin(self.binned)
+            rebin(self.binned, check=False)
             accel(self.binned, self.gm, compensated=self.compensated, plummer=self.plummer,
                   out=self.out)
 
     def replay(self) -> List[torch.Tensor]:
         self.graph.replay()
         return self.out
+
+    def nbad(self) -> List[int]:
+        """Per box, the positions of the last replay that were not finite
+        (their box's forces are then meaningless)."""
+        return self.binned.nbad()

@@ -151,6 +151,16 @@ def test_stepping_calls_reject_bad_arguments(lib):
     assert L.nf_kick_drift(1, good, p1, p1, p1, float("nan"), 0.1, ws, 1 << 20, None) == lib.NF_EINVAL
     assert L.nf_kick_drift(1, good, p1, p1, nul, 0.1, 0.1, ws, 1 << 20, None) == lib.NF_EINVAL
     assert L.nf_kick_drift(1, good, p1, p1, p1, 0.1, 0.1, ws, 16, None) == lib.NF_EWORKSPACE
+    # the step choice: positive finite constants, non-NULL arrays, a workspace
+    assert L.nf_step_choose(1, good, p1, p1, g, 0.03, 1.0, 0.15, None, ws, 1 << 20,
+                            None) == lib.NF_EINVAL
+    assert L.nf_step_choose(1, good, nul, p1, g, 0.03, 1.0, 0.15, g, ws, 1 << 20,
+                            None) == lib.NF_EINVAL
+    for bad in ((0.0, 1.0, 0.15), (0.03, 0.0, 0.15), (0.03, 1.0, -1.0),
+                (float("inf"), 1.0, 0.15), (0.03, float("nan"), 0.15)):
+        assert L.nf_step_choose(1, good, p1, p1, g, *bad, g, ws, 1 << 20, None) == lib.NF_EINVAL
+    assert L.nf_step_choose(1, good, p1, p1, g, 0.03, 1.0, 0.15, g, None, 1 << 20,
+                            None) == lib.NF_EWORKSPACE
 
 
 def test_size_limits_of_the_32bit_index_range(lib):

@@ -81,7 +81,11 @@ def test_bin_empty_box_and_nonfinite():
     torch.cuda.synchronize()
     assert (b.boxes[0].cell_start.cpu().numpy() == 0).all()
     pos = np.array([[0.1, 0.2, 0.3], [np.nan, 0.5, 0.5], [0.7, np.inf, 0.1], [0.4, 0.4, 4e62]])
-    b = nfp.bin_particles(_gpu(pos), K, L, 0.01)
+    with pytest.raises(ValueError, match="non-finite"):
+        nfp.bin_particles(_gpu(pos), K, L, 0.01)
+    with pytest.raises(ValueError, match="non-finite"):
+        nfp.nearfield_accel(_gpu(pos), K, L, 0.01)
+    b = nfp.bin_particles(_gpu(pos), K, L, 0.01, check=False)
     torch.cuda.synchronize()
     assert b.nbad() == [3]
     order = b.boxes[0].order.cpu().numpy()

@@ -40,9 +40,52 @@ def test_step_stats_and_choice(name):
     vel = _t(gaussian_cotangent(sp.n, 17), torch.float32)
     amax, vrms, glob = nfp.step_stats(b, acc, vel)
     ra, rv, rg = _check_stats(pos, sp.K, sp.L, acc.cpu().numpy(), vel.cpu().numpy(), amax, vrms, glob)
-    kw = dict(dlna_max=0.03, hubble=1.0, eta=0.15, cell_width=sp.L / sp.K)
-    assert nfp.choose_step(amax, vrms, glob, **kw) == pytest.approx(
-        oracle.choose_step(ra, rv, rg, **kw), rel=1e-6)
+    kw = dict(dlna_max=0.03, hubble=1.0, eta=0.15)
+    bounds = nfp.step_bounds(b, amax, vrms, glob, **kw).cpu().numpy()[0]
+    # on the library's own statistics the step choice is the oracle's double
+    # sequence: bitwise
+    mine = oracle.step_bounds(amax.cpu().numpy(), vrms.cpu().numpy(), glob.cpu().numpy(),
+                              cell_width=sp.L / sp.K, **kw)
+    assert bounds.tobytes() == np.array(list(mine) + [min(mine)]).tobytes()
+    # and on the oracle's statistics within the float rounding of the cell values
+    ref = oracle.step_bounds(ra, rv, rg, cell_width=sp.L / sp.K, **kw)
+    np.testing.assert_allclose(bounds[:3], ref, rtol=1e-6)
+    assert nfp.choose_step(b, amax, vrms, glob, **kw) == min(mine)
+
+
+def test_step_choice_cases():
+    """The step choice through the library on hand-set statistics of three
+    boxes: the per-cell ratio binding (a cold cell raised to the global
+    ratio), the drift bound binding, and a box with no motion (a_max = 0 and
+    v_max = 0: both ratios +inf, the ln a bound wins)."""
+    specs = [(np.random.default_rng(40 + k).random((50, 3)) * L, K, L)
+             for k, (K, L) in enumerate([(5, 1.0), (6, 2.0), (7, 0.5)])]
+    b = nfp.bin_particles_batched([_t(p, torch.float64) for p, _, _ in specs],
+                                  [K for _, K, _ in specs], [L for _, _, L in specs], [0.01] * 3)
+    rng = np.random.default_rng(44)
+    am, vr, gl = [], [], []
+    for k, (_, K, _) in enumerate(specs):
+        a = rng.uniform(0.5, 2.0, K ** 3).astype(np.float32)
+        v = rng.uniform(0.1, 1.0, K ** 3).astype(np.float32)
+        a[rng.random(K ** 3) < 0.3] = 0.0
+        g = [2.0, 1.0, 3.0]
+        if k == 0:
+            v[5], a[5] = 1e-6, 2.0          # a cold cell: the global ratio takes over
+        if k == 1:
+            g = [1.0, 50.0, 1e4]            # a fast particle: the drift bound binds
+        if k == 2:
+            a[:], v[:], g = 0.0, 0.0, [0.0, 0.0, 0.0]
+        am.append(a)
+        vr.append(v)
+        gl.append(g)
+    kw = dict(dlna_max=0.5, hubble=0.7, eta=0.2)
+    out = nfp.step_bounds(b, [_t(a, torch.float32) for a in am], [_t(v, torch.float32) for v in vr],
+                          _t(np.array(gl), torch.float64), **kw).cpu().numpy()
+    for k, (_, K, L) in enumerate(specs):
+        ref = oracle.step_bounds(am[k], vr[k], np.array(gl[k]), cell_width=L / K, **kw)
+        assert out[k].tobytes() == np.array(list(ref) + [min(ref)]).tobytes(), (k, out[k], ref)
+    assert out[0, 1] == 0.2 * 0.5 and out[1, 3] == out[1, 2] and np.isinf(out[2, 1:3]).all()
+    assert out[2, 3] == 0.5 / 0.7
 
 
 def test_kick_drift_bit_exact_and_batched():
