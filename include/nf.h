@@ -55,7 +55,7 @@
 extern "C" {
 #endif
 
-#define NF_ABI_VERSION 1
+#define NF_ABI_VERSION 2
 
 /* Status codes. */
 enum {
@@ -117,6 +117,27 @@ enum {
  * Requirements: n >= 0, 5 <= K (K = 2R+1 with R = 2; smaller grids would
  * alias the 5x5x5 block), K^3 + 1 <= 2^31 - 1, n <= 2^31 - 1, L and eps_s
  * finite and > 0.  Pointers may be NULL only when n == 0 (cell_start never).
+ *
+ * Tile choices (dense_min and the four fields after nbad; 0 everywhere picks
+ * the library defaults).  The force kernels cut the sinks of a cell into
+ * chunks of 64 and sort the chunks into three occupancy classes: a chunk of
+ * at least dense_min sinks is dense (one sink per lane, sources broadcast);
+ * a smaller last chunk is light (sinks spread over (sink, source-slice) lanes
+ * of four waves, sources staged in LDS), or narrow below narrow_max sinks
+ * (the same on one wave).  The choices change only speed and the FP32
+ * summation order, never which pairs are summed:
+ *   dense_min      2..65, default 41
+ *   narrow_max     1..64, default 12 (1: no narrow items)
+ *   light_window   sources staged per round by a light item: 512, 1024
+ *                  (default) or 2048; the VJP stages 512, 768 or 1536
+ *   narrow_window  the same for narrow items: 128, 256 (default) or 512; the
+ *                  VJP stages 128, 192 or 384
+ *   flush          compensated mode: the plain FP32 partial sums folded into
+ *                  the compensated sum hold at most this many terms, 1..256,
+ *                  default 32 (1 compensates every term)
+ * The windows select kernel instances, so all boxes of one call must agree on
+ * them (0 and the default are the same choice).  The workspace size depends
+ * on dense_min only.
  */
 typedef struct nf_box {
     int64_t n;
@@ -134,6 +155,10 @@ typedef struct nf_box {
     int32_t *cell_start;
     int32_t *order;
     int32_t *nbad;
+    int32_t narrow_max;
+    int32_t light_window;
+    int32_t narrow_window;
+    int32_t flush;
 } nf_box;
 
 /* Library version (NF_ABI_VERSION). */

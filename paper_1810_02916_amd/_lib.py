@@ -55,6 +55,10 @@ class NfBox(ctypes.Structure):
         ("cell_start", ctypes.c_void_p),
         ("order", ctypes.c_void_p),
         ("nbad", ctypes.c_void_p),
+        ("narrow_max", ctypes.c_int32),
+        ("light_window", ctypes.c_int32),
+        ("narrow_window", ctypes.c_int32),
+        ("flush", ctypes.c_int32),
     ]
 
 

@@ -98,6 +98,7 @@ struct Layout {
     size_t total = 0;
     int64_t nblk = 0;
     int passes = 0;
+    int light_window = kDefaultLightWindow, narrow_window = kDefaultNarrowWindow;
 };
 
 int validate(int nbox, const nf_box *boxes, Layout &L) {
@@ -121,6 +122,24 @@ int validate(int nbox, const nf_box *boxes, Layout &L) {
         if (!B.cell_start) return fail(NF_EINVAL, std::string(where) + "cell_start is NULL");
         if (B.dense_min != 0 && (B.dense_min < 2 || B.dense_min > 65))
             return fail(NF_EINVAL, std::string(where) + "dense_min must be 0 or in [2, 65]");
+        if (B.narrow_max < 0 || B.narrow_max > 64)
+            return fail(NF_EINVAL, std::string(where) + "narrow_max must be 0 or in [1, 64]");
+        if (B.flush < 0 || B.flush > 256)
+            return fail(NF_EINVAL, std::string(where) + "flush must be 0 or in [1, 256]");
+        const int lw = B.light_window ? B.light_window : kDefaultLightWindow;
+        const int nw = B.narrow_window ? B.narrow_window : kDefaultNarrowWindow;
+        if (lw != 512 && lw != 1024 && lw != 2048)
+            return fail(NF_EINVAL, std::string(where) + "light_window must be 0, 512, 1024 or 2048");
+        if (nw != 128 && nw != 256 && nw != 512)
+            return fail(NF_EINVAL, std::string(where) + "narrow_window must be 0, 128, 256 or 512");
+        if (b == 0) {
+            L.light_window = lw;
+            L.narrow_window = nw;
+        } else if (lw != L.light_window || nw != L.narrow_window) {
+            return fail(NF_EINVAL, std::string(where) +
+                                       "light_window and narrow_window must agree across the "
+                                       "boxes of a call");
+        }
         if (B.n > 0 && (!B.off || !B.order))
             return fail(NF_EINVAL, std::string(where) + "off/order is NULL");
         const double kappa = (double)B.K / B.L;
@@ -249,6 +268,8 @@ void fill_geometry(const nf_box &B, const Layout &L, int b, DevBox &d, bool plum
     d.plummer = plummer ? 1 : 0;
     d.r2floor = plummer ? (float)(eps * eps) : kR2Floor;
     d.dense_min = B.dense_min ? B.dense_min : kDefaultDenseMin;
+    d.narrow_max = B.narrow_max ? B.narrow_max : kDefaultNarrowMax;
+    d.flush = B.flush ? B.flush : kDefaultFlush;
     d.pos = B.pos;
     d.off = reinterpret_cast<float4 *>(B.off);
     d.cell_start = B.cell_start;
@@ -441,6 +462,8 @@ static int force_common(int nbox, const nf_box *boxes, double gm, uint32_t flags
         tp.dense = reinterpret_cast<Item *>(w + L.dense_off);
         tp.light = reinterpret_cast<Item *>(w + L.light_off);
         tp.counter = reinterpret_cast<uint32_t *>(w + L.counter_off);
+        tp.light_window = L.light_window;
+        tp.narrow_window = L.narrow_window;
         e = vjp ? gather_cot_launch(d_tab, nbox, p, s) : hipSuccess;
         if (e == hipSuccess) e = plan_launch(d_tab, nbox, tp, s);
         if (e == hipSuccess)

@@ -19,7 +19,12 @@ __device__ __forceinline__ gptr<T> gp(T *p) {
 }
 
 // Radix sort geometry: 8-bit digits, 256 threads per block, 16 keys per thread.
-constexpr int kDefaultDenseMin = 41;   // nf_box.dense_min == 0
+// Tile defaults (an nf_box field of 0 picks these).
+constexpr int kDefaultDenseMin = 41;      // nf_box.dense_min
+constexpr int kDefaultNarrowMax = 12;     // nf_box.narrow_max
+constexpr int kDefaultFlush = 32;         // nf_box.flush
+constexpr int kDefaultLightWindow = 1024; // nf_box.light_window (512 / 1024 / 2048)
+constexpr int kDefaultNarrowWindow = 256; // nf_box.narrow_window (128 / 256 / 512)
 // Smallest float added to r^2 for Eq. 2: keeps rsq finite for coincident
 // pairs, whose force is then min(poly, inf) * 0 = 0, and is far below half an
 // ulp of any separation that floats resolve between offsets of order one.
@@ -52,7 +57,9 @@ struct DevBox {
     float scale;          // gm * kappa^2 (accel) or gm * kappa^3 (vjp)
     float cA, cB, cC;     // Eq. 2 in cell widths: F/r = cA + cB r + cC r^2 inside eps
                           // (10/eps^3, -15/eps^4, 6/eps^5, rounded from double)
-    int32_t dense_min;    // cells with at least this many particles take the dense path
+    int32_t dense_min;    // a last chunk of at least this many sinks is dense
+    int32_t narrow_max;   // a light item of fewer sinks is narrow
+    int32_t flush;        // compensated mode: terms per plain partial sum
     int32_t outer_newton; // 1 when eps <= 1: every pair from the outer shell of
                           // the 5x5x5 block is at r >= 1 >= eps (Newton branch)
     float r2floor;        // added to r^2: 1e-30 for Eq. 2 (a coincident pair then

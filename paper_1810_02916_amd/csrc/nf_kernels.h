@@ -40,6 +40,8 @@ struct TilePlan {
     Item *dense = nullptr;       // dense items, heaviest first
     Item *light = nullptr;       // light items, then narrow items, each in spatial slabs
     uint32_t *counter = nullptr; // [queue_words()] queue counters
+    int light_window = 1024;     // staged sources per round: 512 / 1024 / 2048 (accel numbers)
+    int narrow_window = 256;     // 128 / 256 / 512
 };
 int plan_buckets();
 int queue_words();

@@ -20,10 +20,14 @@
 //               segments; the g sinks are spread over the 256 threads as
 //               (sink a, source slice b), thread = a + g b, P = 256 / g
 //               slices, summed at the end by a fixed-order pairwise tree.
-//   * narrow -- a light item of fewer than kNarrow sinks: the same kernel on
-//               one wave per workgroup (P = 64 / g), so the per-item costs
-//               that do not shrink with g (item setup, the per-wave header,
-//               the slice tree) are paid by one wave instead of four.
+//   * narrow -- a light item of fewer than narrow_max sinks (12 by default):
+//               the same kernel on one wave per workgroup (P = 64 / g), so the
+//               per-item costs that do not shrink with g (item setup, the
+//               per-wave header, the slice tree) are paid by one wave instead
+//               of four.
+// The class boundaries (dense_min, narrow_max), the staging windows of the
+// light and narrow kernels and the compensated partial-sum length are tile
+// choices of the caller (nf_box), picked by the autotuner.
 // In both paths a source of the sink's own cell is used unshifted, so the
 // closest pairs are formed from the exact float offsets, and a cell of the
 // outer shell of the block (some |d| = 2) is at r >= 1 and takes the Newton
@@ -46,9 +50,7 @@ constexpr int kQueueStride = 32;     // words between queue counters (own 128-by
 constexpr int kLightWaves = 4;       // waves sharing one light item
 constexpr int kLightThreads = 64 * kLightWaves;
 constexpr int kNarrowThreads = 64;   // one wave per narrow item
-constexpr int kNarrow = 12;          // light items of fewer sinks are narrow
 constexpr int kRows = 25;            // (dx, dy) rows of the 5x5x5 block
-constexpr int kFlush = 32;           // compensated mode: plain partials of <= 32 terms
 
 __device__ __forceinline__ int wrapk(int c, int K) { return c < 0 ? c + K : (c >= K ? c - K : c); }
 __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
@@ -83,7 +85,7 @@ __device__ __forceinline__ int cost_bucket(float pairs) {
 
 // Items of a cell of n particles: n / 64 full dense chunks, and the last
 // n % 64 sinks as one more dense chunk if they are at least dense_min, else as
-// one light item (a narrow one below kNarrow sinks).  cellinfo packs
+// one light item (a narrow one below narrow_max sinks).  cellinfo packs
 // (dense bucket + 1) | (light bucket + 1) << 16, 0 for none; the item counts
 // per (kind, bucket) are summed in LDS first so that each block adds one value
 // per non-empty bucket.
@@ -91,9 +93,9 @@ struct CellItems {
     int ndense;     // dense chunks
     int light;      // kind of the remainder's item: 0 none, 1 light, 2 narrow
 };
-__device__ __forceinline__ CellItems cell_items(int n, int dense_min) {
+__device__ __forceinline__ CellItems cell_items(int n, int dense_min, int narrow_max) {
     const int full = n / kUnit, rem = n % kUnit;
-    const int lk = (rem > 0 && rem < dense_min) ? (rem < kNarrow ? 2 : 1) : 0;
+    const int lk = (rem > 0 && rem < dense_min) ? (rem < narrow_max ? 2 : 1) : 0;
     return CellItems{full + (rem >= dense_min ? 1 : 0), lk};
 }
 
@@ -109,7 +111,7 @@ k_plan_count(const DevBox *boxes, uint32_t *cellinfo, uint32_t *bucket_cnt) {
         const int n = cs[c + 1] - cs[c];
         uint32_t info = 0;
         if (n > 0) {
-            const CellItems it = cell_items(n, B.dense_min);
+            const CellItems it = cell_items(n, B.dense_min, B.narrow_max);
             if (it.ndense) {   // S (the block's sources) ranks dense items only
                 const int K = B.K;
                 const float S = (float)block_sources(cs, K, c / (K * K), (c / K) % K, c % K);
@@ -169,7 +171,7 @@ k_plan_emit(const DevBox *boxes, const uint32_t *__restrict__ cellinfo,
         info = cellinfo[B.cellbase + c];
         if (info) {
             n = gp(B.cell_start)[c + 1] - gp(B.cell_start)[c];
-            it = cell_items(n, B.dense_min);
+            it = cell_items(n, B.dense_min, B.narrow_max);
             bd = (int)(info & 0xffffu) - 1;
             bl = (int)(info >> 16) - 1;
             if (it.ndense) rd = atomicAdd(&h[bd], (uint32_t)it.ndense);
@@ -323,10 +325,14 @@ __device__ __forceinline__ float4 ld_global4(gfloat *p, int64_t i) {
 template <int MODE, bool SPLINE, bool COMP>
 __device__ __forceinline__ void run_scalar(cfloat *__restrict__ src, cfloat *__restrict__ cot,
                                            int j0, int j1, float xs, float ys, float zs,
-                                           float4 vi, const Coef &k, Acc &acc) {
+                                           float4 vi, const Coef &k, int flush, Acc &acc) {
+    // the block's first source through a 64-bit address (4 j0 passes 2^31 for
+    // j0 >= 2^29); inside a block (at most 256 sources) 32-bit offsets
+    constexpr int W = MODE == 0 ? 4 : 8;   // floats per source
+    cfloat *p = src + (int64_t)W * j0;
     int j = j0;
     while (j < j1) {
-        const int blk = min(j1 - j, kFlush);
+        const int blk = min(j1 - j, flush);
         float px = 0.f, py = 0.f, pz = 0.f;
         if constexpr (!COMP) {
             px = acc.x;
@@ -334,18 +340,20 @@ __device__ __forceinline__ void run_scalar(cfloat *__restrict__ src, cfloat *__r
             pz = acc.z;
         }
 #pragma unroll(MODE == 0 ? 4 : 2)
-        for (int t = 0; t < blk; ++t, ++j) {
+        for (int t = 0; t < blk; ++t) {
             if constexpr (MODE == 0) {
-                cfloat *sj = src + 4 * (int64_t)j;   // 64-bit: 4 j passes 2^31 for j >= 2^29
-                pair_accel<SPLINE>(sj[0], sj[1], sj[2], xs, ys, zs, k, px, py, pz);
+                pair_accel<SPLINE>(p[4 * t], p[4 * t + 1], p[4 * t + 2], xs, ys, zs, k, px, py,
+                                   pz);
             } else {
                 // one 32-byte record per source (offset, cotangent), one scalar load
-                const rec8 r8 = ((crec8 *)src)[j];
+                const rec8 r8 = ((crec8 *)p)[t];
                 pair_vjp<SPLINE>(r8[0], r8[1], r8[2], r8[4], r8[5], r8[6], xs, ys, zs, vi.x,
                                  vi.y, vi.z, k,
                                  px, py, pz);
             }
         }
+        p += W * blk;
+        j += blk;
         if constexpr (COMP) {
             fold<true>(acc, px, py, pz);
         } else {
@@ -391,6 +399,7 @@ k_dense(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
         const Coef k{B.cA, B.cB, B.cC, 2.0f * B.cC, B.eps * B.eps, B.r2floor};
         const bool fast = B.outer_newton != 0;
         const bool plummer = B.plummer != 0;   // Plummer law: one branch for every pair
+        const int flush = uni(B.flush);
         cfloat *src = (cfloat *)B.off;
         // the VJP reads sources from the 32-byte records (offset, cotangent)
         cfloat *cot = (cfloat *)(cot_sorted + 2 * B.base);
@@ -422,9 +431,11 @@ k_dense(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
                     if (j0 >= j1) continue;
                     const float zs = oi.z - (float)dz;
                     if (!plummer && (!fast || (in_row && dz >= -1 && dz <= 1)))
-                        run_scalar<MODE, true, COMP>(src, cot, j0, j1, xs, ys, zs, vi, k, acc);
+                        run_scalar<MODE, true, COMP>(src, cot, j0, j1, xs, ys, zs, vi, k, flush,
+                                                     acc);
                     else
-                        run_scalar<MODE, false, COMP>(src, cot, j0, j1, xs, ys, zs, vi, k, acc);
+                        run_scalar<MODE, false, COMP>(src, cot, j0, j1, xs, ys, zs, vi, k, flush,
+                                                      acc);
                 }
             }
         }
@@ -462,13 +473,13 @@ struct LightSmem {
 template <int MODE, bool SPLINE, bool COMP>
 __device__ __forceinline__ void segment(const float4 *__restrict__ sx, const float2 *__restrict__ sv,
                                         int lo, int hi, int b, int P, float xi, float yi,
-                                        float zi, float4 vi, const Coef &k, Acc &acc) {
+                                        float zi, float4 vi, const Coef &k, int flush, Acc &acc) {
     const int n = hi - lo;
     const int nfull = n / P;
     int j = lo + b;
     int it = 0;
     while (it < nfull) {
-        const int blk = min(nfull - it, kFlush);
+        const int blk = min(nfull - it, flush);
         float px = 0.f, py = 0.f, pz = 0.f;
         if constexpr (!COMP) {
             px = acc.x;
@@ -563,6 +574,7 @@ k_light(const DevBox *__restrict__ boxes, const Item *__restrict__ all_items,
         // ---- this lane's sink (sink a, source slice b), loaded before the setup
         const Coef k{B.cA, B.cB, B.cC, 2.0f * B.cC, B.eps * B.eps, B.r2floor};
         const bool fast = B.outer_newton != 0;
+        const int flush = uni(B.flush);
         const int P = NT / g;
         const bool active = lane < g * P;
         const int a = active ? lane % g : 0;
@@ -747,10 +759,10 @@ k_light(const DevBox *__restrict__ boxes, const Item *__restrict__ all_items,
                 const int mid = min(max(split, u0), u1) - u0, hi = u1 - u0;
                 if (mid > 0)
                     segment<MODE, true, COMP>(sm.sx, sm.sv, 0, mid, b, P, oi.x, oi.y, oi.z, vi, k,
-                                              acc);
+                                              flush, acc);
                 if (hi > mid)
                     segment<MODE, false, COMP>(sm.sx, sm.sv, mid, hi, b, P, oi.x, oi.y, oi.z, vi,
-                                               k, acc);
+                                               k, flush, acc);
             }
         }
         // ---- fixed-order pairwise sum over slices: slice b adds slice b + half
@@ -858,55 +870,81 @@ hipError_t side_stream(SideStream &out) {   // caller holds g_side_mu
     return hipSuccess;
 }
 
+// One light-kernel instance (NT threads per item, CAP staged sources per
+// round) on its persistent grid: every queue needs at least one workgroup,
+// so the grid is a multiple of kQueues.
+template <int MODE, bool COMP, int CAP, int NT>
+hipError_t launch_light_inst(const DevBox *d_boxes, const TilePlan &tp, const float4 *cot,
+                             uint32_t *counter, int cls, hipStream_t s) {
+    static const int grid =
+        (persistent_grid(k_light<MODE, COMP, CAP, NT>, NT) + kQueues - 1) / kQueues * kQueues;
+    hipLaunchKernelGGL((k_light<MODE, COMP, CAP, NT>), dim3(grid), dim3(NT), 0, s, d_boxes,
+                       (const Item *)tp.light, (const uint32_t *)tp.totals, counter, cot, cls);
+    return hipGetLastError();
+}
+
+// Light items: windows of 512 / 1024 / 2048 sources (the VJP, whose staged
+// sources take 24 bytes instead of 16: 512 / 768 / 1536).
+template <int MODE, bool COMP>
+hipError_t launch_light(const DevBox *d_boxes, const TilePlan &tp, const float4 *cot,
+                        hipStream_t s) {
+    uint32_t *q = tp.counter + kQueueStride;
+    switch (tp.light_window) {
+        case 512: return launch_light_inst<MODE, COMP, 512, kLightThreads>(d_boxes, tp, cot, q, 1, s);
+        case 2048:
+            return launch_light_inst<MODE, COMP, MODE == 0 ? 2048 : 1536, kLightThreads>(
+                d_boxes, tp, cot, q, 1, s);
+        default:
+            return launch_light_inst<MODE, COMP, MODE == 0 ? 1024 : 768, kLightThreads>(
+                d_boxes, tp, cot, q, 1, s);
+    }
+}
+
+// Narrow items: windows of 128 / 256 / 512 sources (VJP: 128 / 192 / 384).
+template <int MODE, bool COMP>
+hipError_t launch_narrow(const DevBox *d_boxes, const TilePlan &tp, const float4 *cot,
+                         hipStream_t s) {
+    uint32_t *q = tp.counter + kQueueStride * (1 + kQueues);
+    switch (tp.narrow_window) {
+        case 128: return launch_light_inst<MODE, COMP, 128, kNarrowThreads>(d_boxes, tp, cot, q, 2, s);
+        case 512:
+            return launch_light_inst<MODE, COMP, MODE == 0 ? 512 : 384, kNarrowThreads>(
+                d_boxes, tp, cot, q, 2, s);
+        default:
+            return launch_light_inst<MODE, COMP, MODE == 0 ? 256 : 192, kNarrowThreads>(
+                d_boxes, tp, cot, q, 2, s);
+    }
+}
+
+template <int MODE, bool COMP>
+hipError_t launch_dense(const DevBox *d_boxes, const TilePlan &tp, const float4 *cot,
+                        hipStream_t s) {
+    static const int grid = persistent_grid(k_dense<MODE, COMP>, kUnit);
+    hipLaunchKernelGGL((k_dense<MODE, COMP>), dim3(grid), dim3(kUnit), 0, s, d_boxes,
+                       (const Item *)tp.dense, (const uint32_t *)tp.totals, tp.counter, cot);
+    return hipGetLastError();
+}
+
 template <int MODE, bool COMP>
 hipError_t launch_force(const DevBox *d_boxes, const TilePlan &tp, const float4 *cot,
                         bool concurrent, hipStream_t s) {
-    constexpr int CAP = MODE == 0 ? 1024 : 768;
-    constexpr int NCAP = MODE == 0 ? 256 : 192;   // narrow items: 4 KB windows (4.5 KB, VJP)
-    static const int gd = persistent_grid(k_dense<MODE, COMP>, kUnit);
-    // every queue needs at least one workgroup: the grids are multiples of kQueues
-    static const int gl =
-        (persistent_grid(k_light<MODE, COMP, CAP, kLightThreads>, kLightThreads) + kQueues - 1) /
-        kQueues * kQueues;
-    static const int gn =
-        (persistent_grid(k_light<MODE, COMP, NCAP, kNarrowThreads>, kNarrowThreads) + kQueues -
-         1) / kQueues * kQueues;
+    hipError_t e;
     if (!concurrent) {   // the three kernels in turn on the caller's stream
-        hipLaunchKernelGGL((k_light<MODE, COMP, CAP, kLightThreads>), dim3(gl),
-                           dim3(kLightThreads), 0, s, d_boxes, (const Item *)tp.light,
-                           (const uint32_t *)tp.totals, tp.counter + kQueueStride, cot, 1);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_light<MODE, COMP, NCAP, kNarrowThreads>), dim3(gn),
-                           dim3(kNarrowThreads), 0, s, d_boxes, (const Item *)tp.light,
-                           (const uint32_t *)tp.totals, tp.counter + kQueueStride * (1 + kQueues),
-                           cot, 2);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL((k_dense<MODE, COMP>), dim3(gd), dim3(kUnit), 0, s, d_boxes,
-                           (const Item *)tp.dense, (const uint32_t *)tp.totals, tp.counter, cot);
-        return hipGetLastError();
+        if ((e = launch_light<MODE, COMP>(d_boxes, tp, cot, s)) != hipSuccess) return e;
+        if ((e = launch_narrow<MODE, COMP>(d_boxes, tp, cot, s)) != hipSuccess) return e;
+        return launch_dense<MODE, COMP>(d_boxes, tp, cot, s);
     }
     std::lock_guard<std::mutex> lk(g_side_mu);
     SideStream ss;
-    hipError_t e = side_stream(ss);
-    if (e != hipSuccess) return e;
+    if ((e = side_stream(ss)) != hipSuccess) return e;
     if ((e = hipEventRecord(ss.fork, s)) != hipSuccess) return e;
     for (int k = 0; k < 2; ++k)
         if ((e = hipStreamWaitEvent(ss.s[k], ss.fork, 0)) != hipSuccess) return e;
-    hipLaunchKernelGGL((k_light<MODE, COMP, CAP, kLightThreads>), dim3(gl), dim3(kLightThreads),
-                       0, ss.s[0], d_boxes, (const Item *)tp.light, (const uint32_t *)tp.totals,
-                       tp.counter + kQueueStride, cot, 1);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_light<MODE, COMP>(d_boxes, tp, cot, ss.s[0])) != hipSuccess) return e;
     if ((e = hipEventRecord(ss.join[0], ss.s[0])) != hipSuccess) return e;
-    hipLaunchKernelGGL((k_light<MODE, COMP, NCAP, kNarrowThreads>), dim3(gn),
-                       dim3(kNarrowThreads), 0, ss.s[1], d_boxes, (const Item *)tp.light,
-                       (const uint32_t *)tp.totals, tp.counter + kQueueStride * (1 + kQueues), cot,
-                       2);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_narrow<MODE, COMP>(d_boxes, tp, cot, ss.s[1])) != hipSuccess) return e;
     if ((e = hipEventRecord(ss.join[1], ss.s[1])) != hipSuccess) return e;
-    hipLaunchKernelGGL((k_dense<MODE, COMP>), dim3(gd), dim3(kUnit), 0, s, d_boxes,
-                       (const Item *)tp.dense, (const uint32_t *)tp.totals, tp.counter, cot);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_dense<MODE, COMP>(d_boxes, tp, cot, s)) != hipSuccess) return e;
     for (int k = 0; k < 2; ++k)
         if ((e = hipStreamWaitEvent(s, ss.join[k], 0)) != hipSuccess) return e;
     return hipSuccess;

@@ -12,6 +12,7 @@ the current stream.
 from __future__ import annotations
 
 import ctypes
+import dataclasses
 from dataclasses import dataclass, field
 from typing import List, Optional, Sequence
 
@@ -22,6 +23,7 @@ from ._lib import NF_COMPENSATED, NF_PLUMMER, NF_SIMPLE, NF_SPLINE_EVERYWHERE, N
 
 __all__ = [
     "SPLINE_PER_PLUMMER",
+    "Tiles",
     "eps_spline_from_plummer",
     "Binned",
     "bin_particles",
@@ -50,6 +52,30 @@ def eps_spline_from_plummer(eps_p: float) -> float:
     return SPLINE_PER_PLUMMER * float(eps_p)
 
 
+@dataclass(frozen=True)
+class Tiles:
+    """Tile choices of the force kernels (nf_box's tile fields; 0 picks the
+    library default).  A cell's sinks are cut into chunks of 64: a chunk of at
+    least ``dense_min`` sinks is dense, a smaller last chunk light, or narrow
+    below ``narrow_max`` sinks; ``light_window`` / ``narrow_window`` are the
+    sources staged per round (512/1024/2048 and 128/256/512); ``flush`` is
+    the length of the plain partial sums of the compensated mode.  They change
+    speed and FP32 summation order only."""
+    dense_min: int = 0
+    narrow_max: int = 0
+    light_window: int = 0
+    narrow_window: int = 0
+    flush: int = 0
+
+    def as_dict(self) -> dict:
+        return {"dense_min": self.dense_min, "narrow_max": self.narrow_max,
+                "light_window": self.light_window, "narrow_window": self.narrow_window,
+                "flush": self.flush}
+
+
+DEFAULT_TILES = Tiles()
+
+
 def _stream_handle(device) -> ctypes.c_void_p:
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
@@ -64,16 +90,18 @@ class _BoxBuffers:
     cell_start: torch.Tensor   # [K^3+1] int32
     order: torch.Tensor        # [n] int32
     nbad: torch.Tensor         # [1] int32
-    dense_min: int = 0         # tile choice (0: library default)
+    tiles: Tiles = DEFAULT_TILES
 
     @property
     def n(self) -> int:
         return int(self.pos.shape[0])
 
     def cstruct(self) -> NfBox:
-        return NfBox(self.n, self.K, self.dense_min, self.L, self.eps_s, self.pos.data_ptr(),
+        t = self.tiles
+        return NfBox(self.n, self.K, t.dense_min, self.L, self.eps_s, self.pos.data_ptr(),
                      self.off.data_ptr(), self.cell_start.data_ptr(), self.order.data_ptr(),
-                     self.nbad.data_ptr())
+                     self.nbad.data_ptr(), t.narrow_max, t.light_window, t.narrow_window,
+                     t.flush)
 
 
 @dataclass
@@ -99,17 +127,25 @@ class Binned:
     def nbad(self) -> List[int]:
         return [int(b.nbad.item()) for b in self.boxes]
 
-    def set_dense_min(self, v: int) -> None:
-        """Change the force kernels' tile choice (0: library default) for all
-        boxes; the workspace grows if the new choice needs more."""
+    @property
+    def tiles(self) -> Tiles:
+        return self.boxes[0].tiles
+
+    def set_tiles(self, tiles: Tiles) -> None:
+        """Change the force kernels' tile choices for all boxes; the
+        workspace grows if the new choices need more."""
         for bx in self.boxes:
-            bx.dense_min = int(v)
+            bx.tiles = tiles
         self._arr = None
         need = _lib.load().nf_workspace_bytes(self.nbox, self.carray(), 0)
         if need == 0:
             _lib.check(_lib.NF_EINVAL)
         if need > self.workspace.numel():
             self.workspace = torch.empty(int(need), dtype=torch.uint8, device=self.device)
+
+    def set_dense_min(self, v: int) -> None:
+        """Change only the dense / light boundary (0: library default)."""
+        self.set_tiles(dataclasses.replace(self.tiles, dense_min=int(v)))
 
 
 def _prep_pos(pos: torch.Tensor) -> torch.Tensor:
@@ -144,9 +180,11 @@ def _check_nbad(b: Binned) -> None:
 
 def bin_particles_batched(positions: Sequence[torch.Tensor], Ks: Sequence[int],
                           Ls: Sequence[float], eps: Sequence[float],
-                          dense_min: int = 0, check: bool = True) -> Binned:
+                          dense_min: int = 0, check: bool = True,
+                          tiles: Optional[Tiles] = None) -> Binned:
     """Bin several boxes in one call (one radix sort over all of them).
-    ``dense_min`` is the force kernels' tile choice (0: library default).
+    ``tiles`` are the force kernels' tile choices (default: the library's);
+    ``dense_min``, if given, overrides theirs.
     ``check``: read back the library's count of non-finite positions and raise
     ValueError if any box has one (one device synchronisation; pass False to
     skip it and inspect ``Binned.nbad()`` yourself)."""
@@ -158,8 +196,11 @@ def bin_particles_batched(positions: Sequence[torch.Tensor], Ks: Sequence[int],
     if any(p.device != dev for p in ps):
         raise ValueError("all boxes must live on one device")
     boxes = [_alloc_box(p, K, L, e) for p, K, L, e in zip(ps, Ks, Ls, eps)]
+    t = tiles if tiles is not None else DEFAULT_TILES
+    if dense_min:
+        t = dataclasses.replace(t, dense_min=int(dense_min))
     for bx in boxes:
-        bx.dense_min = int(dense_min)
+        bx.tiles = t
     arr = (NfBox * len(boxes))()
     for i, b in enumerate(boxes):
         arr[i] = b.cstruct()
@@ -192,9 +233,10 @@ def rebin(b: Binned, check: bool = True) -> Binned:
 
 
 def bin_particles(pos: torch.Tensor, K: int, L: float, eps_s: float,
-                  dense_min: int = 0, check: bool = True) -> Binned:
+                  dense_min: int = 0, check: bool = True,
+                  tiles: Optional[Tiles] = None) -> Binned:
     """Bin one box: cell offsets (FP64 -> FP32) and a stable sort by cell."""
-    return bin_particles_batched([pos], [K], [L], [eps_s], dense_min, check)
+    return bin_particles_batched([pos], [K], [L], [eps_s], dense_min, check, tiles)
 
 
 def _flags(compensated: bool, simple: bool, plummer: bool = False,
@@ -423,12 +465,15 @@ class CapturedForce:
     the last replay) before trusting its forces."""
 
     def __init__(self, positions: Sequence[torch.Tensor], Ks, Ls, eps, gm: float = 1.0,
-                 compensated: bool = False, plummer: bool = False):
+                 compensated: bool = False, plummer: bool = False,
+                 tiles: Optional[Tiles] = None):
+        """``tiles``: the force kernels' tile choices, e.g. the autotuner's
+        (``tune.tune(...).tiles``); default: the library's."""
         self.positions = [_prep_pos(p) for p in positions]
         self.gm = float(gm)
         self.compensated = bool(compensated)
         self.plummer = bool(plummer)
-        self.binned = bin_particles_batched(self.positions, Ks, Ls, eps)
+        self.binned = bin_particles_batched(self.positions, Ks, Ls, eps, tiles=tiles)
         self.out = [torch.empty((bx.n, 3), dtype=torch.float32, device=self.binned.device)
                     for bx in self.binned.boxes]
         accel(self.binned, self.gm, compensated=self.compensated, plummer=self.plummer,
