@@ -56,6 +56,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle (no errors, no baseline)")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the nested records of the other workloads")
+    ap.add_argument("--serial", action="store_true",
+                    help="force kernels one after another (per-kernel profiles); value is "
+                         "then not the product configuration")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
     return ap.parse_args()
@@ -456,13 +459,13 @@ def main():
         b = nfp.bin_particles(pos, sp.K, sp.L, sp.eps_s, check=False)
         if ev is not None:
             ev[1].record(stream)
-        a0 = nfp.accel(b, 1.0)
+        a0 = nfp.accel(b, 1.0, serial=args.serial)
         if ev is not None:
             ev[2].record(stream)
-        a1 = nfp.accel(b, 1.0, compensated=True)
+        a1 = nfp.accel(b, 1.0, compensated=True, serial=args.serial)
         if ev is not None:
             ev[3].record(stream)
-        g = nfp.accel_vjp(b, cot, 1.0, compensated=True)
+        g = nfp.accel_vjp(b, cot, 1.0, compensated=True, serial=args.serial)
         if ev is not None:
             ev[4].record(stream)
         return b, a0, a1, g
@@ -554,6 +557,7 @@ def main():
             "workload": sp.name, "n": sp.n, "K": sp.K, "L": sp.L, "eps_s": sp.eps_s,
             "sigma_ln": sp.sigma_ln, "interactions": I, "max_cell": occ["max_cell"],
             "step": "bin + accel plain + accel compensated + vjp compensated",
+            "force_kernels": "one after another" if args.serial else "concurrent",
         },
         "breakdown_ms": {"bin": round(t_bin, 4), "accel_plain": round(t_plain, 4),
                          "accel_compensated": round(t_comp, 4), "vjp_compensated": round(t_vjp, 4)},

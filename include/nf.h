@@ -86,7 +86,11 @@ enum {
        same branch as before, so results differ only in the FP32 summation
        order (the light kernel then slices one segment instead of two); the
        point is the cost (for measurement). */
-    NF_SPLINE_EVERYWHERE = 1u << 3
+    NF_SPLINE_EVERYWHERE = 1u << 3,
+    /* Run the dense, light and narrow kernels one after another on the
+       caller's stream instead of side by side on the library's side streams
+       (same results, bitwise; for measuring each kernel on its own). */
+    NF_SERIAL = 1u << 4
 };
 
 /* Upper bound on boxes per call. */

@@ -403,7 +403,8 @@ static int force_common(int nbox, const nf_box *boxes, double gm, uint32_t flags
     int rc = validate(nbox, boxes, L);
     if (rc) return rc;
     if (!std::isfinite(gm)) return fail(NF_EINVAL, "gm must be finite");
-    if (flags & ~(uint32_t)(NF_COMPENSATED | NF_SIMPLE | NF_PLUMMER | NF_SPLINE_EVERYWHERE))
+    if (flags & ~(uint32_t)(NF_COMPENSATED | NF_SIMPLE | NF_PLUMMER | NF_SPLINE_EVERYWHERE |
+                            NF_SERIAL))
         return fail(NF_EINVAL, "unknown flag bits");
     if (!out) return fail(NF_EINVAL, "output pointer array is NULL");
     if (vjp && !cot) return fail(NF_EINVAL, "cotangent pointer array is NULL");
@@ -467,7 +468,8 @@ static int force_common(int nbox, const nf_box *boxes, double gm, uint32_t flags
         e = vjp ? gather_cot_launch(d_tab, nbox, p, s) : hipSuccess;
         if (e == hipSuccess) e = plan_launch(d_tab, nbox, tp, s);
         if (e == hipSuccess)
-            e = tile_launch(d_tab, vjp ? 1 : 0, p.compensated, tp, p.cot_sorted, !noalloc, s);
+            e = tile_launch(d_tab, vjp ? 1 : 0, p.compensated, tp, p.cot_sorted,
+                            !noalloc && !(flags & NF_SERIAL), s);
     }
     if (e != hipSuccess) return fail(NF_EHIP, std::string("force launch: ") + hipGetErrorString(e));
     g_last_error.clear();

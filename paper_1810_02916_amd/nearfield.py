@@ -19,7 +19,8 @@ from typing import List, Optional, Sequence
 import torch
 
 from . import _lib
-from ._lib import NF_COMPENSATED, NF_PLUMMER, NF_SIMPLE, NF_SPLINE_EVERYWHERE, NfBox
+from ._lib import (NF_COMPENSATED, NF_PLUMMER, NF_SERIAL, NF_SIMPLE, NF_SPLINE_EVERYWHERE,
+                   NfBox)
 
 __all__ = [
     "SPLINE_PER_PLUMMER",
@@ -240,10 +241,11 @@ def bin_particles(pos: torch.Tensor, K: int, L: float, eps_s: float,
 
 
 def _flags(compensated: bool, simple: bool, plummer: bool = False,
-           spline_everywhere: bool = False) -> int:
+           spline_everywhere: bool = False, serial: bool = False) -> int:
     return ((NF_COMPENSATED if compensated else 0) | (NF_SIMPLE if simple else 0)
             | (NF_PLUMMER if plummer else 0)
-            | (NF_SPLINE_EVERYWHERE if spline_everywhere else 0))
+            | (NF_SPLINE_EVERYWHERE if spline_everywhere else 0)
+            | (NF_SERIAL if serial else 0))
 
 
 def _ptr_array(tensors: Sequence[torch.Tensor]):
@@ -254,19 +256,21 @@ def _ptr_array(tensors: Sequence[torch.Tensor]):
 
 
 def accel(b: Binned, gm: float = 1.0, *, compensated: bool = False, simple: bool = False,
-          plummer: bool = False, spline_everywhere: bool = False,
+          plummer: bool = False, spline_everywhere: bool = False, serial: bool = False,
           out: Optional[List[torch.Tensor]] = None):
     """Near-field accelerations, float32 [n,3] in input order (a list for
     several boxes).  ``plummer``: the Plummer law of Sec. 4.3 with each box's
     softening length read as eps_p, instead of Eq. 2.  ``spline_everywhere``:
-    the outer-shell shortcut off (same results, for measurement)."""
+    the outer-shell shortcut off (same results, for measurement).
+    ``serial``: the three force kernels one after another (same results, for
+    measuring each kernel alone)."""
     lib = _lib.load()
     if out is None:
         out = [torch.empty((bx.n, 3), dtype=torch.float32, device=b.device) for bx in b.boxes]
     ptrs = _ptr_array(out)
     with torch.cuda.device(b.device):
         rc = lib.nf_accel(b.nbox, b.carray(), float(gm),
-                          _flags(compensated, simple, plummer, spline_everywhere), ptrs,
+                          _flags(compensated, simple, plummer, spline_everywhere, serial), ptrs,
                           ctypes.c_void_p(b.workspace.data_ptr()), b.workspace.numel(),
                           _stream_handle(b.device))
     _lib.check(rc)
@@ -291,7 +295,7 @@ def accel_noalloc(b: Binned, gm: float = 1.0, *, compensated: bool = False,
 
 
 def accel_vjp(b: Binned, cot, gm: float = 1.0, *, compensated: bool = False,
-              simple: bool = False, plummer: bool = False):
+              simple: bool = False, plummer: bool = False, serial: bool = False):
     """Vector-Jacobian product of the accelerations w.r.t. positions
     (cell assignment held fixed); float32 [n,3] per box."""
     lib = _lib.load()
@@ -304,7 +308,8 @@ def accel_vjp(b: Binned, cot, gm: float = 1.0, *, compensated: bool = False,
             raise ValueError("cotangent must have shape (n, 3)")
     grads = [torch.empty((bx.n, 3), dtype=torch.float32, device=b.device) for bx in b.boxes]
     with torch.cuda.device(b.device):
-        rc = lib.nf_accel_vjp(b.nbox, b.carray(), float(gm), _flags(compensated, simple, plummer),
+        rc = lib.nf_accel_vjp(b.nbox, b.carray(), float(gm),
+                              _flags(compensated, simple, plummer, serial=serial),
                               _ptr_array(cots), _ptr_array(grads),
                               ctypes.c_void_p(b.workspace.data_ptr()), b.workspace.numel(),
                               _stream_handle(b.device))

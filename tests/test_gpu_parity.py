@@ -513,3 +513,18 @@ def test_concurrent_callers_on_two_streams():
         for r in results[i]:
             for got, ref in zip(r, alone[i]):
                 assert torch.equal(got, ref), names[i]
+
+
+def test_serial_kernels_equal_concurrent_bitwise():
+    """NF_SERIAL runs the three force kernels one after another on the
+    caller's stream; each item's result depends only on its inputs, so the
+    outputs equal the concurrent launch bitwise."""
+    sp = WORKLOADS["clustered262k"]
+    pos = make_box(sp)
+    b = nfp.bin_particles(_gpu(pos), sp.K, sp.L, sp.eps_s)
+    v = torch.from_numpy(gaussian_cotangent(sp.n, 55).astype(np.float32)).to(DEV)
+    for comp in (False, True):
+        assert torch.equal(nfp.accel(b, 1.0, compensated=comp, serial=True),
+                           nfp.accel(b, 1.0, compensated=comp))
+        assert torch.equal(nfp.accel_vjp(b, v, 1.0, compensated=comp, serial=True),
+                           nfp.accel_vjp(b, v, 1.0, compensated=comp))
