@@ -370,12 +370,13 @@ def rec_clustered134m(args, stream, with_cpu: bool) -> dict:
     t_p = ev_time(stream, lambda: nfp.accel(b, 1.0), reps)
     t_c = ev_time(stream, lambda: nfp.accel(b, 1.0, compensated=True), reps)
     t_v = ev_time(stream, lambda: nfp.accel_vjp(b, cot, 1.0, compensated=True), reps)
+    t_s = ev_time(stream, lambda: nfp.accel(b, 1.0, compensated=True, symmetric=True), reps)
     step = t_bin + t_p + t_c + t_v
     rec = {"n": sp.n, "K": sp.K, "L": sp.L, "sigma_ln": sp.sigma_ln, "interactions": I,
            "pairs_by_kernel": pairs,
            "ms": {"bin": round(t_bin, 3), "accel_plain": round(t_p, 3),
                   "accel_compensated": round(t_c, 3), "vjp_compensated": round(t_v, 3),
-                  "step": round(step, 3)},
+                  "accel_compensated_symmetric": round(t_s, 3), "step": round(step, 3)},
            "value": round(3.0 * I / (step * 1e-3) / 1e9, 3),
            "gdips": {"accel_plain": round(I / t_p / 1e6, 2),
                      "accel_compensated": round(I / t_c / 1e6, 2),
@@ -388,6 +389,7 @@ def rec_clustered134m(args, stream, with_cpu: bool) -> dict:
         s_t = torch.from_numpy(sinks).to(dev)
         ap = nfp.accel(b, 1.0)[s_t].cpu().numpy()
         ac = nfp.accel(b, 1.0, compensated=True)[s_t].cpu().numpy()
+        asym = nfp.accel(b, 1.0, compensated=True, symmetric=True)[s_t].cpu().numpy()
         gv = nfp.accel_vjp(b, cot, 1.0, compensated=True)[s_t].cpu().numpy()
         v = cot.cpu().numpy().astype(np.float64)
         del cot, b
@@ -406,6 +408,7 @@ def rec_clustered134m(args, stream, with_cpu: bool) -> dict:
         exg = oracle.jvp(pos_np, sp.K, sp.L, sp.eps_s, v, sinks=sinks)
         rdg = oracle.jvp(pos_np, sp.K, sp.L, sp.eps_s, v, sinks=sinks, round_offsets=True)
         rec["err_vs_fp64"] = {"plain": err_block(ap, ex, rd), "compensated": err_block(ac, ex, rd),
+                              "compensated_symmetric": err_block(asym, ex, rd),
                               "vjp_compensated": err_block(gv, exg, rdg),
                               "sinks": int(len(sinks)),
                               "sample": f"{len(sinks)} sinks: 8192 random plus up to 512 from "
@@ -510,6 +513,8 @@ def main():
     t_plum = ev_time(stream, lambda: nfp.accel(b, 1.0, plummer=True), reps)
     t_full = ev_time(stream, lambda: nfp.accel(b, 1.0, spline_everywhere=True), reps)
     t_noalloc = ev_time(stream, lambda: nfp.accel_noalloc(b, 1.0, compensated=True), reps)
+    t_sym = ev_time(stream, lambda: nfp.accel(b, 1.0, compensated=True, symmetric=True), reps)
+    a_sym = nfp.accel(b, 1.0, compensated=True, symmetric=True)
     t_mom = ev_time(stream, lambda: nfp.multipoles(b, 8), reps)
     vel = torch.randn((sp.n, 3), generator=torch.Generator(device=dev).manual_seed(sp.seed * 10 + 3),
                       device=dev, dtype=torch.float32)
@@ -525,6 +530,10 @@ def main():
     extras = {
         "plummer_accel_plain": {"ms": round(t_plum, 4), "gdips": round(I / t_plum / 1e6, 2)},
         "accel_plain_shortcut_off": {"ms": round(t_full, 4), "gdips": round(I / t_full / 1e6, 2)},
+        "accel_compensated_symmetric": {"ms": round(t_sym, 4), "gdips": round(I / t_sym / 1e6, 2),
+                                        "engaged": not bool(torch.equal(a_sym, a_comp)),
+                                        "vs_gather": round(t_comp / t_sym, 4),
+                                        "note": "Newton's third law between dense cells"},
         "accel_compensated_noalloc": {"ms": round(t_noalloc, 4),
                                       "gdips": round(I / t_noalloc / 1e6, 2),
                                       "note": "static scratch, the three kernels in turn"},
@@ -608,6 +617,7 @@ def main():
         rndg = oracle.jvp(pos_np, sp.K, sp.L, sp.eps_s, v64, sinks=sv, round_offsets=True)
         ap = a_plain.cpu().numpy()[sinks]
         ac = a_comp.cpu().numpy()[sinks]
+        asym = a_sym.cpu().numpy()[sinks]
         gv = g.cpu().numpy()[sv]
         result["cpu_baseline"] = {
             "value": round(cnt / (tc1 - tc0) / 1e9, 4), "unit": "G pair-interactions/s",
@@ -623,6 +633,7 @@ def main():
         }
         result["err_vs_fp64"] = {
             "plain": err_block(ap, ref, rnd), "compensated": err_block(ac, ref, rnd),
+            "compensated_symmetric": err_block(asym, ref, rnd),
             "vjp_compensated": err_block(gv, refg, rndg),
             "sinks": m, "vjp_sinks": int(len(sv)),
             "note": "e2e: against the oracle on exact offsets; kernel: against the oracle on "

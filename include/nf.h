@@ -90,7 +90,20 @@ enum {
     /* Run the dense, light and narrow kernels one after another on the
        caller's stream instead of side by side on the library's side streams
        (same results, bitwise; for measuring each kernel on its own). */
-    NF_SERIAL = 1u << 4
+    NF_SERIAL = 1u << 4,
+    /* Newton's third law between dense cells (nf_accel only): every pair lies
+       in exactly one of the near and far fields (Sec. 2.1) and the force of
+       Eq. 2 is odd in r, so for two cells of 1 to 16 chunks of 64 sinks, all
+       summed by the dense kernel, in each other's 5x5x5 block, each pair is
+       evaluated once and applied to both particles.  The partial sums are
+       combined in a fixed order (bitwise reproducible); the results differ
+       from the gather form only in FP32 summation order.  Needs the workspace
+       that nf_workspace_bytes reports with this flag (about 520 bytes per
+       particle more: room for 16 partial sums per particle); a call whose
+       symmetric plan outgrows it runs in the gather form.  At most 2^27
+       particles per call (NF_EUNSUPPORTED); not with NF_SIMPLE,
+       nf_accel_vjp or nf_accel_noalloc. */
+    NF_PAIR_SYMMETRIC = 1u << 5
 };
 
 /* Upper bound on boxes per call. */

@@ -22,6 +22,7 @@ NF_SIMPLE = 1 << 1
 NF_PLUMMER = 1 << 2
 NF_SPLINE_EVERYWHERE = 1 << 3
 NF_SERIAL = 1 << 4
+NF_PAIR_SYMMETRIC = 1 << 5
 
 NF_MAX_BOXES = 4096
 NF_MAX_ORDER = 8

@@ -19,7 +19,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libnf.so")
 
-SOURCES = ["nf_api.hip", "nf_bin.hip", "nf_accel.hip", "nf_tile.hip", "nf_multipole.hip", "nf_step.hip"]
+SOURCES = ["nf_api.hip", "nf_bin.hip", "nf_accel.hip", "nf_tile.hip", "nf_pair.hip",
+           "nf_multipole.hip", "nf_step.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -95,13 +95,17 @@ struct Layout {
     int64_t mp_max_pieces = 0;
     int64_t max_dense = 0;
     size_t accel_end = 0;   // bytes an accelerations call uses (table + planner)
+    // pair symmetry (flag NF_PAIR_SYMMETRIC), after the planner's tables
+    size_t f4P_off = 0, f4nf_off = 0, f4slot_off = 0, f4item_cnt_off = 0, f4scan_off = 0,
+           f4tot_off = 0, f4items_off = 0, f4part_off = 0, f4blk_off = 0;
+    uint32_t f4cap_slots = 0, f4cap_items = 0;
     size_t total = 0;
     int64_t nblk = 0;
     int passes = 0;
     int light_window = kDefaultLightWindow, narrow_window = kDefaultNarrowWindow;
 };
 
-int validate(int nbox, const nf_box *boxes, Layout &L) {
+int validate(int nbox, const nf_box *boxes, Layout &L, uint32_t flags = 0) {
     if (nbox < 1 || nbox > NF_MAX_BOXES)
         return fail(NF_EINVAL, "nbox must be in [1, NF_MAX_BOXES]");
     if (!boxes) return fail(NF_EINVAL, "boxes is NULL");
@@ -202,7 +206,33 @@ int validate(int nbox, const nf_box *boxes, Layout &L) {
     L.accel_end = o;
     L.cot_off = o;   // VJP source records: 32 bytes per particle
     o = align_up(o + 32 * (size_t)L.N, 256);
-    const size_t force_end = o;
+    size_t force_end = o;
+    if (flags & NF_PAIR_SYMMETRIC) {   // accelerations only: overlaps the VJP records
+        if (L.N > ((int64_t)1 << 27))   // keeps 16 N + 65536 partial slots in 32 bits
+            return fail(NF_EUNSUPPORTED, "NF_PAIR_SYMMETRIC supports up to 2^27 particles");
+        L.f4cap_slots = (uint32_t)(16 * L.N + 65536);
+        L.f4cap_items = (uint32_t)(L.N / 8 + 1024);
+        o = L.accel_end;
+        L.f4P_off = o;
+        o = align_up(o + 4 * (size_t)L.C, 256);
+        L.f4nf_off = o;
+        o = align_up(o + 4 * (size_t)L.C, 256);
+        L.f4slot_off = o;
+        o = align_up(o + 4 * (size_t)(L.C + 1), 256);
+        L.f4item_cnt_off = o;
+        o = align_up(o + 4 * (size_t)(L.C + 1), 256);
+        L.f4scan_off = o;
+        o = align_up(o + 4 * (size_t)scan_scratch_words(L.C + 1), 256);
+        L.f4tot_off = o;
+        o = align_up(o + 16, 256);
+        L.f4blk_off = o;   // 2 x 8 bytes per block of 256 cells of every box
+        o = align_up(o + 16 * (size_t)(nbox * ((L.max_ncell + 255) / 256) + 1), 256);
+        L.f4items_off = o;
+        o = align_up(o + sizeof(PairItem) * (size_t)L.f4cap_items, 256);
+        L.f4part_off = o;
+        o = align_up(o + 2 * sizeof(float4) * (size_t)L.f4cap_slots, 256);
+        force_end = std::max(force_end, o);
+    }
     // step-statistics scratch, also over the binning scratch region
     o = scratch0;
     L.stepio_off = o;
@@ -340,10 +370,9 @@ const char *nf_strerror(int status) {
 const char *nf_last_error(void) { return g_last_error.c_str(); }
 
 size_t nf_workspace_bytes(int nbox, const nf_box *boxes, uint32_t flags) {
-    (void)flags;
     try {
         Layout L;
-        if (validate(nbox, boxes, L) != NF_OK) return 0;
+        if (validate(nbox, boxes, L, flags) != NF_OK) return 0;
         g_last_error.clear();
         return L.total;
     } catch (...) {
@@ -399,13 +428,18 @@ int nf_bin_particles(int nbox, const nf_box *boxes, void *ws, size_t ws_bytes, v
 static int force_common(int nbox, const nf_box *boxes, double gm, uint32_t flags,
                         const float *const *cot, float *const *out, void *ws, size_t ws_bytes,
                         void *stream, bool vjp, bool noalloc = false) {
+    if (flags & ~(uint32_t)(NF_COMPENSATED | NF_SIMPLE | NF_PLUMMER | NF_SPLINE_EVERYWHERE |
+                            NF_SERIAL | NF_PAIR_SYMMETRIC))
+        return fail(NF_EINVAL, "unknown flag bits");
+    const bool f4 = (flags & NF_PAIR_SYMMETRIC) != 0;
+    if (f4 && vjp) return fail(NF_EINVAL, "NF_PAIR_SYMMETRIC applies to nf_accel only");
+    if (f4 && (flags & NF_SIMPLE)) return fail(NF_EINVAL, "NF_PAIR_SYMMETRIC excludes NF_SIMPLE");
+    if (f4 && noalloc)
+        return fail(NF_EUNSUPPORTED, "NF_PAIR_SYMMETRIC needs a workspace (not allocation-free)");
     Layout L;
-    int rc = validate(nbox, boxes, L);
+    int rc = validate(nbox, boxes, L, f4 ? (uint32_t)NF_PAIR_SYMMETRIC : 0u);
     if (rc) return rc;
     if (!std::isfinite(gm)) return fail(NF_EINVAL, "gm must be finite");
-    if (flags & ~(uint32_t)(NF_COMPENSATED | NF_SIMPLE | NF_PLUMMER | NF_SPLINE_EVERYWHERE |
-                            NF_SERIAL))
-        return fail(NF_EINVAL, "unknown flag bits");
     if (!out) return fail(NF_EINVAL, "output pointer array is NULL");
     if (vjp && !cot) return fail(NF_EINVAL, "cotangent pointer array is NULL");
     for (int b = 0; b < nbox; ++b) {
@@ -430,6 +464,27 @@ static int force_common(int nbox, const nf_box *boxes, double gm, uint32_t flags
         if ((rc = check_ws(L, ws, ws_bytes))) return rc;
         if ((rc = check_device(why))) return fail(rc, why);
     }
+    char *w = static_cast<char *>(ws);
+    F4Plan fp;
+    const bool use_f4 = f4 && L.N > 0;
+    if (use_f4) {
+        fp.C = L.C;
+        fp.max_cells = L.max_ncell;
+        fp.P = reinterpret_cast<int32_t *>(w + L.f4P_off);
+        fp.nfwd = reinterpret_cast<int32_t *>(w + L.f4nf_off);
+        fp.slotoff = reinterpret_cast<uint32_t *>(w + L.f4slot_off);
+        fp.itemoff = reinterpret_cast<uint32_t *>(w + L.f4item_cnt_off);
+        fp.scan = reinterpret_cast<uint32_t *>(w + L.f4scan_off);
+        fp.tot = reinterpret_cast<uint32_t *>(w + L.f4tot_off);
+        fp.blk = reinterpret_cast<uint64_t *>(w + L.f4blk_off);
+        fp.items = reinterpret_cast<PairItem *>(w + L.f4items_off);
+        fp.part = reinterpret_cast<float4 *>(w + L.f4part_off);
+        fp.cap_slots = L.f4cap_slots;
+        fp.cap_items = L.f4cap_items;
+        // the pair kernel's queue is the last kQueueStride words of the counters
+        fp.counter = reinterpret_cast<uint32_t *>(w + L.counter_off) + queue_words() -
+                     f4_queue_words();
+    }
     std::vector<DevBox> tab((size_t)nbox);
     for (int b = 0; b < nbox; ++b) {
         fill_geometry(boxes[b], L, b, tab[b], (flags & NF_PLUMMER) != 0,
@@ -438,9 +493,15 @@ static int force_common(int nbox, const nf_box *boxes, double gm, uint32_t flags
         tab[b].scale = (float)(vjp ? gm * k * k * k : gm * k * k);
         tab[b].out = out[b];
         tab[b].cot = vjp ? cot[b] : nullptr;
+        if (use_f4) {
+            tab[b].f4tot = fp.tot;
+            tab[b].f4P = fp.P;
+            tab[b].f4nf = fp.nfwd;
+            tab[b].f4off = fp.slotoff;
+            tab[b].f4part = fp.part;
+        }
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
-    char *w = static_cast<char *>(ws);
     DevBox *d_tab = reinterpret_cast<DevBox *>(w + L.table_off);
     hipError_t e = upload(tab.data(), sizeof(DevBox) * tab.size(), d_tab, s);
     if (e != hipSuccess) return fail(NF_EHIP, std::string("upload: ") + hipGetErrorString(e));
@@ -467,9 +528,11 @@ static int force_common(int nbox, const nf_box *boxes, double gm, uint32_t flags
         tp.narrow_window = L.narrow_window;
         e = vjp ? gather_cot_launch(d_tab, nbox, p, s) : hipSuccess;
         if (e == hipSuccess) e = plan_launch(d_tab, nbox, tp, s);
+        if (e == hipSuccess && use_f4) e = f4_plan_launch(d_tab, nbox, fp, s);
         if (e == hipSuccess)
             e = tile_launch(d_tab, vjp ? 1 : 0, p.compensated, tp, p.cot_sorted,
-                            !noalloc && !(flags & NF_SERIAL), s);
+                            !noalloc && !(flags & NF_SERIAL), s, use_f4 ? &fp : nullptr);
+        if (e == hipSuccess && use_f4) e = f4_combine_launch(d_tab, nbox, fp, p.compensated, s);
     }
     if (e != hipSuccess) return fail(NF_EHIP, std::string("force launch: ") + hipGetErrorString(e));
     g_last_error.clear();

@@ -72,8 +72,53 @@ struct DevBox {
     int32_t *nbad;        // [1] or null
     float *out;           // acc or grad, [n][3], caller order
     const float *cot;     // [n][3] cotangent (vjp), caller order
+    // pair symmetry (NF_PAIR_SYMMETRIC): per-call arrays over all boxes' cells
+    // (index cellbase + cell), null when off
+    const uint32_t *f4tot;   // [0] 1 when the plan fits (the path is on)
+    const int32_t *f4P;      // partial sums per sink (0: not a symmetric cell)
+    const int32_t *f4nf;     // partners of higher id
+    const uint32_t *f4off;   // first partial slot of the cell
+    float4 *f4part;          // partial sums, slot-major per cell
 };
 static_assert(sizeof(DevBox) % 8 == 0, "DevBox must stay 8-byte aligned");
+
+// Cells whose pairs with each other are evaluated once (NF_PAIR_SYMMETRIC):
+// 1 to kF4MaxChunks chunks of 64 sinks, every chunk summed by the dense
+// kernel (the count is a multiple of 64 or its last chunk holds at least
+// dense_min sinks).
+constexpr int kF4MaxChunks = 16;
+__device__ __forceinline__ bool f4_symmetric_cell(int n, int dense_min) {
+    const int rem = n & 63;
+    return n > 0 && n <= 64 * kF4MaxChunks && (rem == 0 || rem >= dense_min);
+}
+
+// The offset (x, y, z) and cz of sorted slot i through a global pointer.
+__device__ __forceinline__ float4 ld_off4(const float4 *off, int64_t i) {
+    const __attribute__((address_space(1))) float *q =
+        (const __attribute__((address_space(1))) float *)off + 4 * i;
+    return make_float4(q[0], q[1], q[2], q[3]);
+}
+
+// Element i of a float4 array through a global-address-space pointer.
+typedef float nf_v4f __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void st_g4(float4 *base, uint64_t i, float x, float y, float z) {
+    __attribute__((address_space(1))) nf_v4f *p =
+        (__attribute__((address_space(1))) nf_v4f *)base + i;
+    nf_v4f v = {x, y, z, 0.f};
+    *p = v;
+}
+__device__ __forceinline__ nf_v4f ld_g4(const float4 *base, uint64_t i) {
+    const __attribute__((address_space(1))) nf_v4f *p =
+        (const __attribute__((address_space(1))) nf_v4f *)base + i;
+    return *p;
+}
+
+// A symmetric pair item: chunk `chunk` of cell `cell` against every chunk of
+// its partner in direction `dir` (rank `rank` among the cell's partners of
+// higher id).
+struct PairItem {
+    int32_t box, cell, chunk, dir, rank, pad;
+};
 
 // One work item of the tiled force kernels: the sinks of cell `cell0` of
 // box `box`, all of them when the cell holds at most 64 particles, else the

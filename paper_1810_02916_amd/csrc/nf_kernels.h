@@ -29,6 +29,27 @@ hipError_t scan_exclusive(uint32_t *data, int64_t M, uint32_t *scratch, hipStrea
 hipError_t fill_u32(uint32_t *p, int64_t count, uint32_t value, hipStream_t s);
 hipError_t bin_launch(const DevBox *d_boxes, int nbox, const BinPlan &p, hipStream_t s);
 
+// Pair symmetry (nf_pair.hip).
+struct F4Plan {
+    int64_t C = 0, max_cells = 0;
+    int32_t *P = nullptr, *nfwd = nullptr;   // [C]
+    uint32_t *slotoff = nullptr;              // [C + 1] counts, then first slots
+    uint32_t *itemoff = nullptr;              // [C + 1] counts, then first items
+    uint32_t *scan = nullptr;                 // scan scratch
+    uint32_t *tot = nullptr;                  // [4] on, items, slots
+    uint64_t *blk = nullptr;                  // [2 x blocks of the count kernel] totals
+    PairItem *items = nullptr;                // [cap_items]
+    float4 *part = nullptr;                   // [cap_slots] (x2 compensated)
+    uint32_t *counter = nullptr;              // item queue
+    uint32_t cap_slots = 0, cap_items = 0;
+};
+int f4_queue_words();
+hipError_t f4_plan_launch(const DevBox *d_boxes, int nbox, const F4Plan &fp, hipStream_t s);
+hipError_t f4_ring_launch(const DevBox *d_boxes, const F4Plan &fp, bool compensated,
+                          hipStream_t s);
+hipError_t f4_combine_launch(const DevBox *d_boxes, int nbox, const F4Plan &fp, bool compensated,
+                             hipStream_t s);
+
 // Planner + tile kernels (nf_tile.hip).
 struct TilePlan {
     int64_t TG = 0;              // cells over all boxes (planning is per cell)
@@ -50,7 +71,8 @@ hipError_t plan_launch(const DevBox *d_boxes, int nbox, const TilePlan &tp, hipS
 // concurrent: the light and narrow kernels run on the library's side streams
 // alongside the dense kernel; otherwise all three run in turn on s.
 hipError_t tile_launch(const DevBox *d_boxes, int mode, bool compensated, const TilePlan &tp,
-                       const float4 *cot, bool concurrent, hipStream_t s);
+                       const float4 *cot, bool concurrent, hipStream_t s,
+                       const F4Plan *f4 = nullptr);
 
 // Per-cell multipole moments (nf_multipole.hip).
 int multipole_max_order();

@@ -400,6 +400,12 @@ k_dense(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
         const bool fast = B.outer_newton != 0;
         const bool plummer = B.plummer != 0;   // Plummer law: one branch for every pair
         const int flush = uni(B.flush);
+        // pair symmetry: the sinks of a symmetric cell skip the sources of
+        // their symmetric partner cells (summed once by the pair kernel) and
+        // leave their sum in partial slot 0
+        const int nX = uni(cs[I.cell0 + 1] - cs[I.cell0]);
+        const bool f4sink = MODE == 0 && B.f4tot != nullptr && uni((int)gp(B.f4tot)[0]) != 0 &&
+                            f4_symmetric_cell(nX, B.dense_min);
         cfloat *src = (cfloat *)B.off;
         // the VJP reads sources from the 32-byte records (offset, cotangent)
         cfloat *cot = (cfloat *)(cot_sorted + 2 * B.base);
@@ -426,9 +432,13 @@ k_dense(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
 #pragma unroll
                 for (int q = 0; q < 5; ++q) {
                     const int dz = q - 2;
-                    const int j0 = max(__builtin_amdgcn_readlane(cb[q], r), 0);
-                    const int j1 = min(__builtin_amdgcn_readlane(ce[q], r), B.n);
+                    const int cbq = __builtin_amdgcn_readlane(cb[q], r);
+                    const int ceq = __builtin_amdgcn_readlane(ce[q], r);
+                    const int j0 = max(cbq, 0);
+                    const int j1 = min(ceq, B.n);
                     if (j0 >= j1) continue;
+                    if (f4sink && !(r == 12 && q == 2) && f4_symmetric_cell(ceq - cbq, B.dense_min))
+                        continue;
                     const float zs = oi.z - (float)dz;
                     if (!plummer && (!fast || (in_row && dz >= -1 && dz <= 1)))
                         run_scalar<MODE, true, COMP>(src, cot, j0, j1, xs, ys, zs, vi, k, flush,
@@ -439,7 +449,20 @@ k_dense(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
                 }
             }
         }
-        if (active) store(B, slot, value<COMP>(acc));
+        if (f4sink) {
+            if (active) {
+                const int64_t gX = B.cellbase + I.cell0;
+                const uint64_t idx = (uint64_t)gp(B.f4off)[gX] + (uint64_t)(kUnit * I.chunk + lane);
+                if constexpr (COMP) {
+                    st_g4(B.f4part, 2 * idx, acc.x, acc.y, acc.z);
+                    st_g4(B.f4part, 2 * idx + 1, -acc.cx, -acc.cy, -acc.cz);
+                } else {
+                    st_g4(B.f4part, idx, acc.x, acc.y, acc.z);
+                }
+            }
+        } else if (active) {
+            store(B, slot, value<COMP>(acc));
+        }
     }
 }
 
@@ -927,12 +950,14 @@ hipError_t launch_dense(const DevBox *d_boxes, const TilePlan &tp, const float4 
 
 template <int MODE, bool COMP>
 hipError_t launch_force(const DevBox *d_boxes, const TilePlan &tp, const float4 *cot,
-                        bool concurrent, hipStream_t s) {
+                        bool concurrent, hipStream_t s, const F4Plan *f4) {
     hipError_t e;
-    if (!concurrent) {   // the three kernels in turn on the caller's stream
+    if (!concurrent) {   // the kernels in turn on the caller's stream
         if ((e = launch_light<MODE, COMP>(d_boxes, tp, cot, s)) != hipSuccess) return e;
         if ((e = launch_narrow<MODE, COMP>(d_boxes, tp, cot, s)) != hipSuccess) return e;
-        return launch_dense<MODE, COMP>(d_boxes, tp, cot, s);
+        if ((e = launch_dense<MODE, COMP>(d_boxes, tp, cot, s)) != hipSuccess) return e;
+        if (f4 && (e = f4_ring_launch(d_boxes, *f4, COMP, s)) != hipSuccess) return e;
+        return hipSuccess;
     }
     std::lock_guard<std::mutex> lk(g_side_mu);
     SideStream ss;
@@ -945,6 +970,7 @@ hipError_t launch_force(const DevBox *d_boxes, const TilePlan &tp, const float4 
     if ((e = launch_narrow<MODE, COMP>(d_boxes, tp, cot, ss.s[1])) != hipSuccess) return e;
     if ((e = hipEventRecord(ss.join[1], ss.s[1])) != hipSuccess) return e;
     if ((e = launch_dense<MODE, COMP>(d_boxes, tp, cot, s)) != hipSuccess) return e;
+    if (f4 && (e = f4_ring_launch(d_boxes, *f4, COMP, s)) != hipSuccess) return e;
     for (int k = 0; k < 2; ++k)
         if ((e = hipStreamWaitEvent(s, ss.join[k], 0)) != hipSuccess) return e;
     return hipSuccess;
@@ -953,7 +979,8 @@ hipError_t launch_force(const DevBox *d_boxes, const TilePlan &tp, const float4 
 }  // namespace
 
 int plan_buckets() { return kKinds * kBuckets; }
-int queue_words() { return (1 + 2 * kQueues) * kQueueStride; }
+// dense queue, light and narrow queues, then the pair kernel's queue
+int queue_words() { return (2 + 2 * kQueues) * kQueueStride; }
 
 hipError_t plan_launch(const DevBox *d_boxes, int nbox, const TilePlan &tp, hipStream_t s) {
     hipError_t e;
@@ -971,14 +998,14 @@ hipError_t plan_launch(const DevBox *d_boxes, int nbox, const TilePlan &tp, hipS
 }
 
 hipError_t tile_launch(const DevBox *d_boxes, int mode, bool compensated, const TilePlan &tp,
-                       const float4 *cot, bool concurrent, hipStream_t s) {
+                       const float4 *cot, bool concurrent, hipStream_t s, const F4Plan *f4) {
     hipError_t e = fill_u32(tp.counter, queue_words(), 0u, s);
     if (e != hipSuccess) return e;
     if (mode == 0)
-        return compensated ? launch_force<0, true>(d_boxes, tp, cot, concurrent, s)
-                           : launch_force<0, false>(d_boxes, tp, cot, concurrent, s);
-    return compensated ? launch_force<1, true>(d_boxes, tp, cot, concurrent, s)
-                       : launch_force<1, false>(d_boxes, tp, cot, concurrent, s);
+        return compensated ? launch_force<0, true>(d_boxes, tp, cot, concurrent, s, f4)
+                           : launch_force<0, false>(d_boxes, tp, cot, concurrent, s, f4);
+    return compensated ? launch_force<1, true>(d_boxes, tp, cot, concurrent, s, nullptr)
+                       : launch_force<1, false>(d_boxes, tp, cot, concurrent, s, nullptr);
 }
 
 }  // namespace nf

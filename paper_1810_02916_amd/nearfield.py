@@ -19,8 +19,8 @@ from typing import List, Optional, Sequence
 import torch
 
 from . import _lib
-from ._lib import (NF_COMPENSATED, NF_PLUMMER, NF_SERIAL, NF_SIMPLE, NF_SPLINE_EVERYWHERE,
-                   NfBox)
+from ._lib import (NF_COMPENSATED, NF_PAIR_SYMMETRIC, NF_PLUMMER, NF_SERIAL, NF_SIMPLE,
+                   NF_SPLINE_EVERYWHERE, NfBox)
 
 __all__ = [
     "SPLINE_PER_PLUMMER",
@@ -144,6 +144,15 @@ class Binned:
         if need > self.workspace.numel():
             self.workspace = torch.empty(int(need), dtype=torch.uint8, device=self.device)
 
+    def ensure_workspace(self, flags: int) -> None:
+        """Grow the workspace to what a call with ``flags`` needs (the pair
+        symmetry flag needs more than binning and the gather form)."""
+        need = _lib.load().nf_workspace_bytes(self.nbox, self.carray(), int(flags))
+        if need == 0:
+            _lib.check(_lib.NF_EINVAL)
+        if need > self.workspace.numel():
+            self.workspace = torch.empty(int(need), dtype=torch.uint8, device=self.device)
+
     def set_dense_min(self, v: int) -> None:
         """Change only the dense / light boundary (0: library default)."""
         self.set_tiles(dataclasses.replace(self.tiles, dense_min=int(v)))
@@ -241,11 +250,13 @@ def bin_particles(pos: torch.Tensor, K: int, L: float, eps_s: float,
 
 
 def _flags(compensated: bool, simple: bool, plummer: bool = False,
-           spline_everywhere: bool = False, serial: bool = False) -> int:
+           spline_everywhere: bool = False, serial: bool = False,
+           symmetric: bool = False) -> int:
     return ((NF_COMPENSATED if compensated else 0) | (NF_SIMPLE if simple else 0)
             | (NF_PLUMMER if plummer else 0)
             | (NF_SPLINE_EVERYWHERE if spline_everywhere else 0)
-            | (NF_SERIAL if serial else 0))
+            | (NF_SERIAL if serial else 0)
+            | (NF_PAIR_SYMMETRIC if symmetric else 0))
 
 
 def _ptr_array(tensors: Sequence[torch.Tensor]):
@@ -257,20 +268,24 @@ def _ptr_array(tensors: Sequence[torch.Tensor]):
 
 def accel(b: Binned, gm: float = 1.0, *, compensated: bool = False, simple: bool = False,
           plummer: bool = False, spline_everywhere: bool = False, serial: bool = False,
-          out: Optional[List[torch.Tensor]] = None):
+          symmetric: bool = False, out: Optional[List[torch.Tensor]] = None):
     """Near-field accelerations, float32 [n,3] in input order (a list for
     several boxes).  ``plummer``: the Plummer law of Sec. 4.3 with each box's
     softening length read as eps_p, instead of Eq. 2.  ``spline_everywhere``:
     the outer-shell shortcut off (same results, for measurement).
     ``serial``: the three force kernels one after another (same results, for
-    measuring each kernel alone)."""
+    measuring each kernel alone).  ``symmetric``: Newton's third law between
+    dense cells (each pair of two such cells evaluated once; the workspace
+    grows on the first such call)."""
     lib = _lib.load()
+    flags = _flags(compensated, simple, plummer, spline_everywhere, serial, symmetric)
+    if symmetric:
+        b.ensure_workspace(flags)
     if out is None:
         out = [torch.empty((bx.n, 3), dtype=torch.float32, device=b.device) for bx in b.boxes]
     ptrs = _ptr_array(out)
     with torch.cuda.device(b.device):
-        rc = lib.nf_accel(b.nbox, b.carray(), float(gm),
-                          _flags(compensated, simple, plummer, spline_everywhere, serial), ptrs,
+        rc = lib.nf_accel(b.nbox, b.carray(), float(gm), flags, ptrs,
                           ctypes.c_void_p(b.workspace.data_ptr()), b.workspace.numel(),
                           _stream_handle(b.device))
     _lib.check(rc)

@@ -197,3 +197,23 @@ def test_noalloc_rejects_without_a_device(lib):
     assert L.nf_accel_noalloc(1, (lib.NfBox * 1)(_box(lib, 10, K=4)), 1.0, 0, outs,
                               None) == lib.NF_EINVAL
     assert lib.NF_NOALLOC_SCRATCH_BYTES == 32 << 20
+
+
+def test_pair_symmetric_flag_validation(lib):
+    """NF_PAIR_SYMMETRIC: accelerations only, not with NF_SIMPLE or the
+    allocation-free entry point; it needs a larger workspace."""
+    L = lib.load()
+    good = (lib.NfBox * 1)(_box(lib, 100000, 32))
+    plain = L.nf_workspace_bytes(1, good, 0)
+    sym = L.nf_workspace_bytes(1, good, lib.NF_PAIR_SYMMETRIC)
+    assert sym > plain
+    ws = ctypes.c_void_p(0x100000)
+    outs = (ctypes.c_void_p * 1)(0x2000)
+    cots = (ctypes.c_void_p * 1)(0x3000)
+    f = lib.NF_PAIR_SYMMETRIC
+    assert L.nf_accel_vjp(1, good, 1.0, f, cots, outs, ws, sym, None) == lib.NF_EINVAL
+    assert L.nf_accel(1, good, 1.0, f | lib.NF_SIMPLE, outs, ws, sym, None) == lib.NF_EINVAL
+    assert L.nf_accel_noalloc(1, good, 1.0, f, outs, None) == lib.NF_EUNSUPPORTED
+    assert L.nf_accel(1, good, 1.0, f, outs, ws, plain, None) == lib.NF_EWORKSPACE
+    big = (lib.NfBox * 1)(_box(lib, (1 << 27) + 1, 32))
+    assert L.nf_workspace_bytes(1, big, f) == 0
