@@ -102,6 +102,8 @@ struct Layout {
     size_t total = 0;
     int64_t nblk = 0;
     int passes = 0;
+    int radix_bits = 8;
+    size_t offc_off = 0;
     int light_window = kDefaultLightWindow, narrow_window = kDefaultNarrowWindow;
 };
 
@@ -163,7 +165,9 @@ int validate(int nbox, const nf_box *boxes, Layout &L, uint32_t flags = 0) {
     if (L.C + 1 > INT32_MAX) return fail(NF_EUNSUPPORTED, "total cells over all boxes exceed 2^31 - 2");
     int bits = 1;
     while (bits < 32 && ((int64_t)1 << bits) < L.C) ++bits;
-    L.passes = (bits + kRadixBits - 1) / kRadixBits;
+    // 8-bit digits, or 9 when that saves a pass (18-bit keys: 2 passes, not 3)
+    L.radix_bits = (bits + 8) / 9 < (bits + 7) / 8 ? 9 : 8;
+    L.passes = (bits + L.radix_bits - 1) / L.radix_bits;
     L.nblk = std::max<int64_t>(1, (L.N + kSortTile - 1) / kSortTile);
 
     size_t o = 0;
@@ -177,13 +181,16 @@ int validate(int nbox, const nf_box *boxes, Layout &L, uint32_t flags = 0) {
         L.vals_off[k] = o;
         o = align_up(o + 4 * (size_t)L.N, 256);
     }
+    L.offc_off = o;
+    o = align_up(o + 16 * (size_t)L.N, 256);
     L.hist_off = o;
-    o = align_up(o + 4 * (size_t)kRadix * (size_t)L.nblk, 256);
+    o = align_up(o + 4 * (size_t)(1 << L.radix_bits) * (size_t)L.nblk, 256);
     L.cellcnt_off = o;
     o = align_up(o + 4 * (size_t)(L.C + 1), 256);
     L.scan_off = o;
     const int64_t scan_words =
-        std::max(scan_scratch_words((int64_t)kRadix * L.nblk), scan_scratch_words(L.C + 1));
+        std::max(scan_scratch_words((int64_t)(1 << L.radix_bits) * L.nblk),
+                 scan_scratch_words(L.C + 1));
     o = align_up(o + 4 * (size_t)scan_words, 256);
     const size_t bin_end = o;
     // force scratch reuses the binning scratch region: the planner's tables
@@ -405,10 +412,12 @@ int nf_bin_particles(int nbox, const nf_box *boxes, void *ws, size_t ws_bytes, v
         p.max_ncell = L.max_ncell;
         p.nblk = L.nblk;
         p.passes = L.passes;
+        p.radix_bits = L.radix_bits;
         for (int k = 0; k < 2; ++k) {
             p.sc.keys[k] = reinterpret_cast<uint32_t *>(w + L.keys_off[k]);
             p.sc.vals[k] = reinterpret_cast<uint32_t *>(w + L.vals_off[k]);
         }
+        p.sc.offc = reinterpret_cast<float4 *>(w + L.offc_off);
         p.sc.hist = reinterpret_cast<uint32_t *>(w + L.hist_off);
         p.sc.cellcnt = reinterpret_cast<uint32_t *>(w + L.cellcnt_off);
         p.scan_scratch = reinterpret_cast<uint32_t *>(w + L.scan_off);

@@ -29,8 +29,6 @@ constexpr int kDefaultNarrowWindow = 256; // nf_box.narrow_window (128 / 256 / 5
 // pairs, whose force is then min(poly, inf) * 0 = 0, and is far below half an
 // ulp of any separation that floats resolve between offsets of order one.
 constexpr float kR2Floor = 1.0e-30f;
-constexpr int kRadixBits = 8;
-constexpr int kRadix = 1 << kRadixBits;
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortThreads * kSortItems;   // 4096 keys per block
@@ -130,8 +128,10 @@ struct Item {
 // Global (all boxes) scratch used by the binning kernels.
 struct BinScratch {
     uint32_t *keys[2];    // [N] concatenated keys (cellbase_b + cell id)
-    uint32_t *vals[2];    // [N] concatenated element index
-    uint32_t *hist;       // [256 * nblk] digit-major block histograms
+    uint32_t *vals[2];    // [N] concatenated element index (vals[0] unused: the
+                          // first pass takes the identity)
+    float4 *offc;         // [N] float offsets and z cell, concatenated caller order
+    uint32_t *hist;       // [radix * nblk] digit-major block histograms
     uint32_t *cellcnt;    // [C + 1] first sorted slot of each concatenated cell key
 };
 
@@ -158,12 +158,13 @@ __device__ __forceinline__ bool cell_coord(double x, double kappa, int K, int &c
     return true;
 }
 
-// Wave-level "match any" on an 8-bit digit: mask of the active lanes whose
+// Wave-level "match any" on a BITS-bit digit: mask of the active lanes whose
 // digit equals this lane's digit.
+template <int BITS>
 __device__ __forceinline__ uint64_t match_digit(bool valid, uint32_t d) {
     uint64_t m = __ballot(valid);
 #pragma unroll
-    for (int b = 0; b < kRadixBits; ++b) {
+    for (int b = 0; b < BITS; ++b) {
         bool bit = (d >> b) & 1u;
         uint64_t bb = __ballot(valid && bit);
         m &= bit ? bb : ~bb;

@@ -17,7 +17,8 @@ struct BinPlan {
     int64_t max_n = 0;      // largest n_b
     int64_t max_ncell = 0;  // largest K_b^3
     int64_t nblk = 0;       // radix tiles: ceil(N / kSortTile)
-    int passes = 0;         // 8-bit radix passes covering keys 0..C-1
+    int passes = 0;         // radix passes covering keys 0..C-1 (at least 1)
+    int radix_bits = 8;     // digit width: 8, or 9 when that saves a pass
     BinScratch sc{};
     uint32_t *scan_scratch = nullptr;
 };

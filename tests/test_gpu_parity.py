@@ -94,6 +94,22 @@ def test_bin_empty_box_and_nonfinite():
     assert sorted(order.tolist()) == [0, 1, 2, 3]
 
 
+@pytest.mark.parametrize("K,n", [(8, 4096 * 3), (50, 200003), (64, 4096 * 50), (81, 300001)])
+def test_bin_digit_widths(K, n):
+    """Key ranges that take one 9-bit pass (K=8), two 9-bit passes (K=50,
+    K=64: 17 and 18 bits) and three 8-bit passes (K=81: 20 bits), over many
+    sort tiles, a full last tile and a ragged one; half the particles in a
+    few dense clusters, the rest uniform, in shuffled order."""
+    rng = np.random.default_rng(K * 1000 + 3)
+    L = 2.0
+    nc = n // 2
+    centres = rng.uniform(0, L, size=(7, 3))
+    clus = centres[rng.integers(0, 7, nc)] + 0.004 * L * rng.standard_normal((nc, 3))
+    pos = np.concatenate([clus, rng.uniform(0, L, size=(n - nc, 3))])[rng.permutation(n)]
+    print(f"[bin] K={K} n={n}", flush=True)
+    _bin_check(pos, K, L)
+
+
 def test_bin_batched_matches_single():
     specs = batched_specs(4, seed=5, lo=4000, hi=9000)
     poss = [make_box(s) for s in specs]
