@@ -1,9 +1,9 @@
 // One wave per workgroup.  Lane u owns a unit: a product x^a y^b and up to
 // four consecutive powers z^c0 .. z^(c0+3) of the same (a, b), so its terms
-// x^a y^b z^c share one product and walk up the z powers by multiplication
-// (61 units cover the 165 terms of order 8).  Particles are staged 32 at a
-// time as double powers x^k, y^k, z^k in LDS (the next 32 offsets are loaded
-// while the current ones are summed).
+// x^a y^b z^c share one product, each added by one fused multiply-add with a
+// staged z power (61 units cover the 165 terms of order 8).  Particles are
+// staged 64 at a time as double powers x^k, y^k, z^k in LDS (the next 64
+// offsets are loaded while the current ones are summed).
 //
 //   k_multipoles  a run of consecutive cells of bounded cost (particles plus
 //                 a fixed cost per cell) per workgroup; each lane adds its
@@ -25,8 +25,13 @@ namespace {
 
 constexpr int kMaxOrder = 8;
 constexpr int kUnitTerms = 4;       // consecutive z powers per lane
-constexpr int kChunk = 32;          // particles staged per round
-constexpr int kPow = 3 * (kMaxOrder + 1);   // x^0..8, y^0..8, z^0..8 of one particle
+constexpr int kChunk = 64;          // particles staged per round (one per lane)
+// staged powers of one particle: x^0..8, y^0..8, then z^0..11 (a unit starting
+// at z^8 reads four; the powers past the order feed terms that are never stored)
+constexpr int kZPow = kMaxOrder + kUnitTerms;
+constexpr int kPow = 2 * (kMaxOrder + 1) + kZPow;
+static_assert(kPow % 2 == 0 && (2 * (kMaxOrder + 1)) % 2 == 0 && kUnitTerms % 2 == 0,
+              "z powers of a unit are read as 16-byte pairs");
 // Work partition: cell c costs its particles plus kCellCost (its T stores);
 // workgroup w takes the cells whose cumulative cost
 //   cost(c) = cell_start[c] + kCellCost * c
@@ -43,7 +48,7 @@ __device__ __forceinline__ int64_t cell_cost(const int32_t *cs, int c) {
 
 // Storage index of term (a, b, c), n = a + b + c: the terms of lower degree,
 // then a descending, then b descending within degree n.
-__device__ __forceinline__ int term_index(int a, int b, int c) {
+constexpr int term_index(int a, int b, int c) {
     const int n = a + b + c;
     return n * (n + 1) * (n + 2) / 6 + (n - a) * (n - a + 1) / 2 + (n - a - b);
 }
@@ -68,75 +73,93 @@ k_mp_ranges(const DevBox *__restrict__ boxes, const int64_t *__restrict__ range_
     for (int64_t w = lo; w <= hi && w < nrange; ++w) f[w] = c;
 }
 
-// This lane's unit: (a, b) pairs in order, each cut into runs of <= 4 z
-// powers; uk = 0 for a lane without a unit.  ia, ib, ic index a particle's
-// staged powers; idx are the storage indices of the unit's terms.
+// The lanes' units for every order p: (a, b) pairs in order, each cut into
+// runs of <= 4 z powers of which the first uk are terms.  ia, ib, ic index a
+// particle's staged powers; idx are the storage indices of the unit's terms,
+// and for j >= uk idx[j] repeats idx[0], so that a lane stores all four slots
+// without a branch (the extra stores rewrite term 0 with its own value).
+// Lanes without a unit repeat lane 0's: they compute and store the same
+// values at the same places.  Built at compile time, read once per workgroup.
 struct LaneUnit {
-    int ia = 0, ib = kMaxOrder + 1, ic = 2 * (kMaxOrder + 1), uk = 0;
-    int idx[kUnitTerms] = {0, 0, 0, 0};
+    int16_t ia, ib, ic, uk;
+    int16_t idx[kUnitTerms];
 };
-__device__ __forceinline__ LaneUnit lane_unit(int p, int t) {
-    int ua = 0, ub = 0, uc = 0, uk = 0;
-    int u = 0;
+struct UnitTable {
+    LaneUnit u[kMaxOrder + 1][64];
+};
+constexpr UnitTable make_units() {
+    UnitTable T{};
+    for (int p = 0; p <= kMaxOrder; ++p) {
+        int n = 0;
+        for (int a = 0; a <= p; ++a)
+            for (int b = 0; a + b <= p; ++b)
+                for (int c = 0; a + b + c <= p; c += kUnitTerms, ++n) {
+                    LaneUnit L{(int16_t)a, (int16_t)(kMaxOrder + 1 + b),
+                               (int16_t)(2 * (kMaxOrder + 1) + c),
+                               (int16_t)(p - a - b - c + 1 < kUnitTerms ? p - a - b - c + 1
+                                                                        : kUnitTerms),
+                               {0, 0, 0, 0}};
+                    for (int j = 0; j < kUnitTerms; ++j)
+                        L.idx[j] = (int16_t)term_index(a, b, j < L.uk ? c + j : c);
+                    T.u[p][n] = L;
+                }
+        for (int t = n; t < 64; ++t) T.u[p][t] = T.u[p][0];
+    }
+    return T;
+}
+constexpr int count_units(int p) {
+    int n = 0;
     for (int a = 0; a <= p; ++a)
         for (int b = 0; a + b <= p; ++b)
-            for (int c = 0; a + b + c <= p; c += kUnitTerms, ++u)
-                if (u == t) {
-                    ua = a;
-                    ub = b;
-                    uc = c;
-                    uk = min(kUnitTerms, p - a - b - c + 1);
-                }
-    LaneUnit L;
-    L.ia = ua;
-    L.ib = kMaxOrder + 1 + ub;
-    L.ic = 2 * (kMaxOrder + 1) + uc;
-    L.uk = uk;
-#pragma unroll
-    for (int j = 0; j < kUnitTerms; ++j) L.idx[j] = term_index(ua, ub, uc + j);
-    return L;
+            for (int c = 0; a + b + c <= p; c += kUnitTerms) ++n;
+    return n;
 }
+static_assert(count_units(kMaxOrder) <= 64, "one unit per lane");
+__constant__ UnitTable kUnits = make_units();
 
-// Lane t < cnt writes the powers 0..p of its particle's offset o.
+__device__ __forceinline__ LaneUnit lane_unit(int p, int t) { return kUnits.u[p][t]; }
+
+// Lane t < cnt writes the powers 0..p of x and y and 0..11 of z of its
+// particle's offset o.
 __device__ __forceinline__ void stage_powers(double (*pw)[kPow], int t, int cnt, int p, float4 o) {
     if (t < cnt) {
         const double x = o.x, y = o.y, z = o.z;
-        double px = 1.0, py = 1.0, pz = 1.0;
+        double px = 1.0, py = 1.0;
         for (int k = 0; k <= p; ++k) {
             pw[t][k] = px;
             pw[t][kMaxOrder + 1 + k] = py;
-            pw[t][2 * (kMaxOrder + 1) + k] = pz;
             px *= x;
             py *= y;
+        }
+        double pz = 1.0;
+#pragma unroll
+        for (int k = 0; k < kZPow; ++k) {
+            pw[t][2 * (kMaxOrder + 1) + k] = pz;
             pz *= z;
         }
     }
 }
 
 // acc[j] += sum over staged particles l in [l0, l1), in order, of
-// x^a y^b z^(c0 + j).  Terms past the unit's last one are computed and never
-// stored.
+// x^a y^b z^(c0 + j), each term one fused multiply-add of the product
+// x^a y^b and the staged z power.  Terms past the unit's last one are computed
+// and never stored.
 __device__ __forceinline__ void add_staged(const double (*pw)[kPow], int l0, int l1,
                                            const LaneUnit &U, double acc[kUnitTerms]) {
-    constexpr int iz = 2 * (kMaxOrder + 1) + 1;   // z^1
     // unrolled so that the loads and products of several particles are in
     // flight at once; only the additions into acc chain
 #pragma unroll 4
     for (int l = l0; l < l1; ++l) {
-        double m = pw[l][U.ia] * pw[l][U.ib];
-        m = m * pw[l][U.ic];
-        const double zz = pw[l][iz];
-        acc[0] += m;
-        m = m * zz;
-        acc[1] += m;
-        m = m * zz;
-        acc[2] += m;
-        m = m * zz;
-        acc[3] += m;
+        const double m = pw[l][U.ia] * pw[l][U.ib];
+        // z^c0 .. z^(c0+3): c0 is a multiple of 4 and rows are 16-byte multiples
+        const double2 z01 = *reinterpret_cast<const double2 *>(&pw[l][U.ic]);
+        const double2 z23 = *reinterpret_cast<const double2 *>(&pw[l][U.ic + 2]);
+        acc[0] = __builtin_fma(m, z01.x, acc[0]);
+        acc[1] = __builtin_fma(m, z01.y, acc[1]);
+        acc[2] = __builtin_fma(m, z23.x, acc[2]);
+        acc[3] = __builtin_fma(m, z23.y, acc[3]);
     }
 }
-
-__device__ __forceinline__ int cell_count(const int *cst, int k) { return cst[k + 1] - cst[k]; }
 
 // The offset of sorted slot i (x, y, z) through a global pointer.
 __device__ __forceinline__ float4 ld_off(gptr<const float> off, int i) {
@@ -147,8 +170,7 @@ __device__ __forceinline__ float4 ld_off(gptr<const float> off, int i) {
 __global__ void __launch_bounds__(64)
 k_multipoles(const DevBox *__restrict__ boxes, const int64_t *__restrict__ range_base,
              const int32_t *__restrict__ first, int p, int nterms) {
-    __shared__ double pw[kChunk][kPow];           // powers of the staged particles
-    __shared__ int cst[kRange / kCellCost + 1];   // cell starts of the range (<= 64 cells)
+    __shared__ __align__(16) double pw[kChunk][kPow];   // powers of the staged particles
     const int box = blockIdx.y;
     const int w = blockIdx.x;
     if ((int64_t)w >= range_base[box + 1] - range_base[box]) return;   // whole workgroup
@@ -163,28 +185,35 @@ k_multipoles(const DevBox *__restrict__ boxes, const int64_t *__restrict__ range
     static_assert(kChunk <= 64, "one staged particle per lane");
     const int c0 = f[w], c1 = f[w + 1];
     if (c0 >= c1) return;
-    // each cell costs >= kCellCost, so a range holds at most kRange / kCellCost cells
-    for (int k = t; k <= c1 - c0; k += 64) cst[k] = cs[c0 + k];
-    __syncthreads();
+    // each cell costs >= kCellCost, so a range holds at most kRange / kCellCost
+    // = 64 cells: lane k holds the start and end of the range's cell k, read
+    // back with readlane (uniform index, no memory wait)
+    static_assert(kRange / kCellCost <= 64, "one cell of the range per lane");
+    const int cbeg_l = t < c1 - c0 ? cs[c0 + t] : 0;
+    const int cend_l = t < c1 - c0 ? cs[c0 + t + 1] : 0;
+    auto cbeg = [&](int cell) { return __builtin_amdgcn_readlane(cbeg_l, cell - c0); };
+    auto cend_of = [&](int cell) { return __builtin_amdgcn_readlane(cend_l, cell - c0); };
     double acc[kUnitTerms] = {0.0, 0.0, 0.0, 0.0};
     auto flush = [&](int cell) {
+        const gptr<float> o = out + (int64_t)cell * nterms;
+        const float v0 = (float)acc[0];
 #pragma unroll
         for (int j = 0; j < kUnitTerms; ++j) {
-            if (j < U.uk) out[(int64_t)cell * nterms + U.idx[j]] = (float)acc[j];
+            o[U.idx[j]] = j < U.uk ? (float)acc[j] : v0;
             acc[j] = 0.0;
         }
     };
     // runs [ca, cb) of cells of at most kBig particles (bounds are uniform)
     for (int ca = c0; ca < c1;) {
-        if (cell_count(cst, ca - c0) > kBig) {
+        if (cend_of(ca) - cbeg(ca) > kBig) {
             ++ca;
             continue;
         }
         int cb = ca + 1;
-        while (cb < c1 && cell_count(cst, cb - c0) <= kBig) ++cb;
-        const int p0 = cst[ca - c0], p1 = cst[cb - c0];
+        while (cb < c1 && cend_of(cb) - cbeg(cb) <= kBig) ++cb;
+        const int p0 = cbeg(ca), p1 = cend_of(cb - 1);
         int cell = ca;
-        int cend = cst[ca - c0 + 1];
+        int cend = cend_of(ca);
         float4 o = make_float4(0.f, 0.f, 0.f, 0.f);
         if (t < kChunk && p0 + t < p1) o = ld_off(off, p0 + t);
         for (int s = p0; s < p1; s += kChunk) {
@@ -197,7 +226,7 @@ k_multipoles(const DevBox *__restrict__ boxes, const int64_t *__restrict__ range
                 while (i >= cend) {     // cells that end at or before particle i
                     flush(cell);
                     ++cell;
-                    cend = cst[cell - c0 + 1];
+                    cend = cend_of(cell);
                 }
                 const int j = min(e, cend);
                 add_staged(pw, i - s, j - s, U, acc);
@@ -240,7 +269,7 @@ k_mp_emit(const DevBox *__restrict__ boxes, const uint32_t *__restrict__ offsets
 __global__ void __launch_bounds__(64)
 k_mp_pieces(const DevBox *__restrict__ boxes, const MpPiece *__restrict__ pieces,
             const uint32_t *__restrict__ total, double *__restrict__ partial, int p) {
-    __shared__ double pw[kChunk][kPow];
+    __shared__ __align__(16) double pw[kChunk][kPow];
     const int w = blockIdx.x;
     if (w >= (int64_t)*total) return;   // whole workgroup
     const MpPiece pc = pieces[w];
@@ -261,7 +290,7 @@ k_mp_pieces(const DevBox *__restrict__ boxes, const MpPiece *__restrict__ pieces
     }
 #pragma unroll
     for (int j = 0; j < kUnitTerms; ++j)
-        if (j < U.uk) partial[(int64_t)w * kMaxTerms + U.idx[j]] = acc[j];
+        partial[(int64_t)w * kMaxTerms + U.idx[j]] = j < U.uk ? acc[j] : acc[0];
 }
 
 // The first piece of each big cell adds the cell's pieces in order.
