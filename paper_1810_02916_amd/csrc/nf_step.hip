@@ -4,8 +4,10 @@
 // the fastest particle crosses 80% of a cell; the step's Kick and Drift
 // stages).
 //
-//   k_step_cells   one wave per cell over the cell-sorted slots: a_max and
-//                  v_rms of the cell (double inside, float out) and the
+//   k_step_cells   a wave per 8 consecutive cells over the cell-sorted
+//                  slots: 8 lanes per cell when none of them holds more than
+//                  64 particles, else the whole wave for each in turn; a_max
+//                  and v_rms of the cell (double inside, float out) and the
 //                  cell's (a_max, sum |v|^2, max |v|^2) in double scratch;
 //   k_step_partial fixed cell ranges per block -> per-block partials;
 //   k_step_final   one block per box -> (a_max, v_rms, v_max) in double.
@@ -27,6 +29,8 @@ namespace {
 
 constexpr int kStatThreads = 256;
 constexpr int kStatWaves = kStatThreads / 64;
+constexpr int kGroup = 8;         // lanes per cell (and cells per wave) for small cells
+constexpr int kGroupMax = 64;     // the largest cell the 8-lane form takes
 
 __device__ __forceinline__ double dsq3(float x, float y, float z) {
 #pragma clang fp contract(off)
@@ -34,15 +38,48 @@ __device__ __forceinline__ double dsq3(float x, float y, float z) {
     return (a * a + b * b) + c * c;
 }
 
-// Butterfly over the 64 lanes: every lane ends with the same value (the
-// pairwise sums are commutative, so each level agrees across the pair).
-__device__ __forceinline__ double wave_sum(double x) {
-    for (int o = 32; o >= 1; o >>= 1) x = __dadd_rn(x, __shfl_xor(x, o));
+// Butterfly over groups of W lanes (W a power of two up to 64): every lane
+// of a group ends with the same value (the pairwise sums are commutative, so
+// each level agrees across the pair).
+template <int W>
+__device__ __forceinline__ double group_sum(double x) {
+    for (int o = W / 2; o >= 1; o >>= 1) x = __dadd_rn(x, __shfl_xor(x, o));
     return x;
 }
-__device__ __forceinline__ double wave_max(double x) {
-    for (int o = 32; o >= 1; o >>= 1) x = fmax(x, __shfl_xor(x, o));
+template <int W>
+__device__ __forceinline__ double group_max(double x) {
+    for (int o = W / 2; o >= 1; o >>= 1) x = fmax(x, __shfl_xor(x, o));
     return x;
+}
+
+// Statistics of cell c over its slots [s0, s1), taken by the W lanes of a
+// group lane-strided (q = the lane's index in the group), then reduced by
+// the group's butterfly; lane q == 0 writes them.
+template <int W>
+__device__ __forceinline__ void cell_stats(const DevBox &B, const StepIO &S, CellStat *scratch,
+                                           int c, int s0, int s1, int q, bool valid) {
+#pragma clang fp contract(off)
+    double am = 0.0, v2 = 0.0, vm = 0.0;
+    for (int s = s0 + q; s < s1; s += W) {
+        const int i = B.order[s];
+        if (i < 0 || i >= B.n) continue;   // never taken for a consistent binning
+        const float *a = S.acc + 3 * (int64_t)i;
+        const float *v = S.vel + 3 * (int64_t)i;
+        const double a2 = dsq3(a[0], a[1], a[2]);
+        const double w2 = dsq3(v[0], v[1], v[2]);
+        am = fmax(am, __dsqrt_rn(a2));
+        v2 = v2 + w2;
+        vm = fmax(vm, w2);
+    }
+    am = group_max<W>(am);
+    v2 = group_sum<W>(v2);
+    vm = group_max<W>(vm);
+    if (valid && q == 0) {
+        const int cnt = s1 - s0;
+        S.amax[c] = (float)am;
+        S.vrms[c] = cnt > 0 ? (float)__dsqrt_rn(__ddiv_rn(v2, (double)cnt)) : 0.0f;
+        scratch[B.cellbase + c] = CellStat{am, v2, vm};
+    }
 }
 
 __global__ void __launch_bounds__(kStatThreads)
@@ -53,28 +90,19 @@ k_step_cells(const DevBox *__restrict__ boxes, const StepIO *__restrict__ io,
     const StepIO &S = io[blockIdx.y];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int32_t *__restrict__ cs = B.cell_start;
-    for (int c = blockIdx.x * kStatWaves + wave; c < B.ncell; c += gridDim.x * kStatWaves) {
-        const int s0 = cs[c], s1 = cs[c + 1];
-        double am = 0.0, v2 = 0.0, vm = 0.0;
-        for (int s = s0 + lane; s < s1; s += 64) {
-            const int i = B.order[s];
-            if (i < 0 || i >= B.n) continue;   // never taken for a consistent binning
-            const float *a = S.acc + 3 * (int64_t)i;
-            const float *v = S.vel + 3 * (int64_t)i;
-            const double a2 = dsq3(a[0], a[1], a[2]);
-            const double w2 = dsq3(v[0], v[1], v[2]);
-            am = fmax(am, __dsqrt_rn(a2));
-            v2 = v2 + w2;
-            vm = fmax(vm, w2);
-        }
-        am = wave_max(am);
-        v2 = wave_sum(v2);
-        vm = wave_max(vm);
-        if (lane == 0) {
-            const int cnt = s1 - s0;
-            S.amax[c] = (float)am;
-            S.vrms[c] = cnt > 0 ? (float)__dsqrt_rn(__ddiv_rn(v2, (double)cnt)) : 0.0f;
-            scratch[B.cellbase + c] = CellStat{am, v2, vm};
+    for (int cb = (blockIdx.x * kStatWaves + wave) * kGroup; cb < B.ncell;
+         cb += gridDim.x * kStatWaves * kGroup) {
+        // lane: cell cb + lane / 8, index lane % 8 in its group
+        const int c = cb + lane / kGroup;
+        const bool valid = c < B.ncell;
+        const int s0 = valid ? cs[c] : 0, s1 = valid ? cs[c + 1] : 0;
+        if (__all(s1 - s0 <= kGroupMax)) {
+            cell_stats<kGroup>(B, S, scratch, c, s0, s1, lane % kGroup, valid);
+        } else {   // a big cell among the eight: each cell by the whole wave
+            for (int k = 0; k < kGroup && cb + k < B.ncell; ++k) {
+                const int cc = cb + k;
+                cell_stats<64>(B, S, scratch, cc, cs[cc], cs[cc + 1], lane, true);
+            }
         }
     }
 }
@@ -218,7 +246,7 @@ k_kick_drift(const DevBox *__restrict__ boxes, const StepIO *__restrict__ io, do
 hipError_t step_stats_launch(const DevBox *d_boxes, const StepIO *d_io, int nbox,
                              int64_t max_ncell, CellStat *scratch, CellStat *partial,
                              double *glob, hipStream_t s) {
-    const int64_t nb = (max_ncell + kStatWaves - 1) / kStatWaves;
+    const int64_t nb = (max_ncell + kStatWaves * kGroup - 1) / (kStatWaves * kGroup);
     const unsigned gx = (unsigned)std::max<int64_t>(1, std::min<int64_t>(nb, 8192));
     hipLaunchKernelGGL(k_step_cells, dim3(gx, (unsigned)nbox), dim3(kStatThreads), 0, s, d_boxes,
                        d_io, scratch);
