@@ -224,8 +224,13 @@ struct Coef {
     float floor;   // added to r^2 (DevBox::r2floor)
 };
 
-// One pair of the acceleration sum; SPLINE selects the single-min form of
-// Eq. 2, otherwise the pair is known to lie outside eps (Newton branch).
+// One pair of the acceleration sum; SPLINE selects Eq. 2's single-min form,
+// otherwise the pair is known to lie outside eps (Newton branch).  Outside
+// eps the spline lies above r^-3 (their difference is 10 (r/eps - 1)^3 in
+// units of eps^-3), so the min form is evaluated only when some lane of the
+// wave has r^2 < eps^2, which few pairs do: a compare per pair instead of
+// the polynomial and the min.  (The empty volatile asm keeps the rare branch
+// a branch instead of letting the compiler evaluate both sides.)
 template <bool SPLINE>
 __device__ __forceinline__ void pair_accel(float sx, float sy, float sz, float xi, float yi,
                                            float zi, const Coef &k, float &px, float &py,
@@ -235,17 +240,59 @@ __device__ __forceinline__ void pair_accel(float sx, float sy, float sz, float x
     r2 = __builtin_fmaf(ry, ry, r2);
     r2 = __builtin_fmaf(rz, rz, r2);
     const float q = __builtin_amdgcn_rsqf(r2);
-    const float q3 = q * q * q;
-    float f;
+    float f = q * q * q;
     if constexpr (SPLINE) {
-        const float rho = r2 * q;
-        f = fminf(__builtin_fmaf(__builtin_fmaf(k.cC, rho, k.cB), rho, k.cA), q3);
-    } else {
-        f = q3;
+        const bool in = r2 < k.eps2;
+        if (__any(in)) {
+            asm volatile("");
+            const float rho = r2 * q;
+            const float g = fminf(__builtin_fmaf(__builtin_fmaf(k.cC, rho, k.cB), rho, k.cA), f);
+            f = in ? g : f;
+        }
     }
     px = __builtin_fmaf(f, rx, px);
     py = __builtin_fmaf(f, ry, py);
     pz = __builtin_fmaf(f, rz, pz);
+}
+
+// Four pairs of the acceleration sum with the sources' offsets in sx, sy,
+// sz, added in order; the spline's branch is taken once for the four.
+template <bool SPLINE>
+__device__ __forceinline__ void pair_accel4(const float (&sx)[4], const float (&sy)[4],
+                                            const float (&sz)[4], float xi, float yi, float zi,
+                                            const Coef &k, float &px, float &py, float &pz) {
+    float rx[4], ry[4], rz[4], r2[4], q[4], f[4];
+    bool in = false;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        rx[u] = sx[u] - xi;
+        ry[u] = sy[u] - yi;
+        rz[u] = sz[u] - zi;
+        r2[u] = __builtin_fmaf(rx[u], rx[u], k.floor);
+        r2[u] = __builtin_fmaf(ry[u], ry[u], r2[u]);
+        r2[u] = __builtin_fmaf(rz[u], rz[u], r2[u]);
+        q[u] = __builtin_amdgcn_rsqf(r2[u]);
+        f[u] = q[u] * q[u] * q[u];
+        if constexpr (SPLINE) in |= r2[u] < k.eps2;
+    }
+    if constexpr (SPLINE) {
+        if (__any(in)) {
+            asm volatile("");
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const float rho = r2[u] * q[u];
+                const float g =
+                    fminf(__builtin_fmaf(__builtin_fmaf(k.cC, rho, k.cB), rho, k.cA), f[u]);
+                f[u] = r2[u] < k.eps2 ? g : f[u];
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        px = __builtin_fmaf(f[u], rx[u], px);
+        py = __builtin_fmaf(f[u], ry[u], py);
+        pz = __builtin_fmaf(f[u], rz[u], pz);
+    }
 }
 
 // One pair of the VJP: xbar_i += g (v_j - v_i) + h (r . (v_j - v_i)) r, with
@@ -339,17 +386,28 @@ __device__ __forceinline__ void run_scalar(cfloat *__restrict__ src, cfloat *__r
             py = acc.y;
             pz = acc.z;
         }
-#pragma unroll(MODE == 0 ? 4 : 2)
-        for (int t = 0; t < blk; ++t) {
-            if constexpr (MODE == 0) {
+        if constexpr (MODE == 0) {
+            int t = 0;
+            for (; t + 4 <= blk; t += 4) {
+                float ax[4], ay[4], az[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    ax[u] = p[4 * (t + u)];
+                    ay[u] = p[4 * (t + u) + 1];
+                    az[u] = p[4 * (t + u) + 2];
+                }
+                pair_accel4<SPLINE>(ax, ay, az, xs, ys, zs, k, px, py, pz);
+            }
+            for (; t < blk; ++t)
                 pair_accel<SPLINE>(p[4 * t], p[4 * t + 1], p[4 * t + 2], xs, ys, zs, k, px, py,
                                    pz);
-            } else {
+        } else {
+#pragma unroll 2
+            for (int t = 0; t < blk; ++t) {
                 // one 32-byte record per source (offset, cotangent), one scalar load
                 const rec8 r8 = ((crec8 *)p)[t];
                 pair_vjp<SPLINE>(r8[0], r8[1], r8[2], r8[4], r8[5], r8[6], xs, ys, zs, vi.x,
-                                 vi.y, vi.z, k,
-                                 px, py, pz);
+                                 vi.y, vi.z, k, px, py, pz);
             }
         }
         p += W * blk;
@@ -509,17 +567,34 @@ __device__ __forceinline__ void segment(const float4 *__restrict__ sx, const flo
             py = acc.y;
             pz = acc.z;
         }
-#pragma unroll 4
-        for (int t = 0; t < blk; ++t) {
-            const float4 s = sx[j];
-            if constexpr (MODE == 0) {
+        if constexpr (MODE == 0) {
+            int t = 0;
+            for (; t + 4 <= blk; t += 4) {
+                float ax[4], ay[4], az[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const float4 s = sx[j + u * P];
+                    ax[u] = s.x;
+                    ay[u] = s.y;
+                    az[u] = s.z;
+                }
+                pair_accel4<SPLINE>(ax, ay, az, xi, yi, zi, k, px, py, pz);
+                j += 4 * P;
+            }
+            for (; t < blk; ++t) {
+                const float4 s = sx[j];
                 pair_accel<SPLINE>(s.x, s.y, s.z, xi, yi, zi, k, px, py, pz);
-            } else {
+                j += P;
+            }
+        } else {
+#pragma unroll 4
+            for (int t = 0; t < blk; ++t) {
+                const float4 s = sx[j];
                 const float2 v = sv[j];
                 pair_vjp<SPLINE>(s.x, s.y, s.z, s.w, v.x, v.y, xi, yi, zi, vi.x, vi.y, vi.z, k,
                                  px, py, pz);
+                j += P;
             }
-            j += P;
         }
         it += blk;
         if constexpr (COMP) {
