@@ -295,44 +295,77 @@ __device__ __forceinline__ void pair_accel4(const float (&sx)[4], const float (&
     }
 }
 
-// One pair of the VJP: xbar_i += g (v_j - v_i) + h (r . (v_j - v_i)) r, with
-// g = F/r and h = g'(rho)/rho.  Inside eps: g = cA + cB rho + cC rho^2 and
-// h = cB / rho + 2 cC = cB q + 2 cC; outside: g = q^3, h = -3 q^5.
+// N pairs of the VJP, added in order: xbar_i += g (v_j - v_i) + h (r .
+// (v_j - v_i)) r, with g = F/r and h = g'(rho)/rho.  Outside eps (Newton, or
+// Plummer through the r^2 floor) g = q^3 and h = -3 q^5, so the term is
+// q^3 (u - 3 q^2 (r.u) r): 23 VALU.  Inside eps g = cA + cB rho + cC rho^2
+// and h = cB / rho + 2 cC = cB q + 2 cC.  With SPLINE the inside form is
+// evaluated only when some lane of the wave has one of the N pairs inside
+// eps (a compare per pair otherwise), as in pair_accel.
+template <bool SPLINE, int N>
+__device__ __forceinline__ void pair_vjpN(const float (&sx)[N], const float (&sy)[N],
+                                          const float (&sz)[N], const float (&vx)[N],
+                                          const float (&vy)[N], const float (&vz)[N], float xi,
+                                          float yi, float zi, float vxi, float vyi, float vzi,
+                                          const Coef &k, float &px, float &py, float &pz) {
+    float rx[N], ry[N], rz[N], ux[N], uy[N], uz[N], r2[N], q[N], rdu[N];
+    bool in = false;
+#pragma unroll
+    for (int u = 0; u < N; ++u) {
+        rx[u] = sx[u] - xi;
+        ry[u] = sy[u] - yi;
+        rz[u] = sz[u] - zi;
+        ux[u] = vx[u] - vxi;
+        uy[u] = vy[u] - vyi;
+        uz[u] = vz[u] - vzi;
+        r2[u] = __builtin_fmaf(rx[u], rx[u], k.floor);
+        r2[u] = __builtin_fmaf(ry[u], ry[u], r2[u]);
+        r2[u] = __builtin_fmaf(rz[u], rz[u], r2[u]);
+        q[u] = __builtin_amdgcn_rsqf(r2[u]);
+        rdu[u] = rx[u] * ux[u];
+        rdu[u] = __builtin_fmaf(ry[u], uy[u], rdu[u]);
+        rdu[u] = __builtin_fmaf(rz[u], uz[u], rdu[u]);
+        if constexpr (SPLINE) in |= r2[u] < k.eps2;
+    }
+    auto newton = [&](int u, float &ax, float &ay, float &az) {
+        const float q2 = q[u] * q[u];
+        const float q3 = q2 * q[u];
+        const float w = (-3.0f * q2) * rdu[u];
+        ax = __builtin_fmaf(q3, __builtin_fmaf(w, rx[u], ux[u]), ax);
+        ay = __builtin_fmaf(q3, __builtin_fmaf(w, ry[u], uy[u]), ay);
+        az = __builtin_fmaf(q3, __builtin_fmaf(w, rz[u], uz[u]), az);
+    };
+    if constexpr (SPLINE) {
+        if (__any(in)) {
+            asm volatile("");   // keep the rare branch a branch
+#pragma unroll
+            for (int u = 0; u < N; ++u) {
+                float nx = px, ny = py, nz = pz;
+                newton(u, nx, ny, nz);
+                const float rho = r2[u] * q[u];
+                const float g = __builtin_fmaf(__builtin_fmaf(k.cC, rho, k.cB), rho, k.cA);
+                const float h = __builtin_fmaf(k.cB, q[u], k.cC2);
+                const float t = h * rdu[u];
+                const bool inside = r2[u] < k.eps2;
+                px = inside ? __builtin_fmaf(t, rx[u], __builtin_fmaf(g, ux[u], px)) : nx;
+                py = inside ? __builtin_fmaf(t, ry[u], __builtin_fmaf(g, uy[u], py)) : ny;
+                pz = inside ? __builtin_fmaf(t, rz[u], __builtin_fmaf(g, uz[u], pz)) : nz;
+            }
+            return;
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < N; ++u) newton(u, px, py, pz);
+}
+
 template <bool SPLINE>
 __device__ __forceinline__ void pair_vjp(float sx, float sy, float sz, float vx, float vy,
                                          float vz, float xi, float yi, float zi, float vxi,
                                          float vyi, float vzi, const Coef &k, float &px,
                                          float &py, float &pz) {
-    const float rx = sx - xi, ry = sy - yi, rz = sz - zi;
-    const float ux = vx - vxi, uy = vy - vyi, uz = vz - vzi;
-    float r2 = __builtin_fmaf(rx, rx, k.floor);
-    r2 = __builtin_fmaf(ry, ry, r2);
-    r2 = __builtin_fmaf(rz, rz, r2);
-    const float q = __builtin_amdgcn_rsqf(r2);
-    const float q2 = q * q;
-    const float q3 = q2 * q;
-    float rdu = rx * ux;
-    rdu = __builtin_fmaf(ry, uy, rdu);
-    rdu = __builtin_fmaf(rz, uz, rdu);
-    if constexpr (SPLINE) {
-        float g = q3, h = -3.0f * q3 * q2;
-        if (r2 < k.eps2) {
-            const float rho = r2 * q;
-            g = __builtin_fmaf(__builtin_fmaf(k.cC, rho, k.cB), rho, k.cA);
-            h = __builtin_fmaf(k.cB, q, k.cC2);
-        }
-        const float t = h * rdu;
-        px = __builtin_fmaf(t, rx, __builtin_fmaf(g, ux, px));
-        py = __builtin_fmaf(t, ry, __builtin_fmaf(g, uy, py));
-        pz = __builtin_fmaf(t, rz, __builtin_fmaf(g, uz, pz));
-    } else {
-        // Newton (or Plummer through the r^2 floor): g u + h (r.u) r with
-        // g = q^3, h = -3 q^5 is q^3 (u - 3 q^2 (r.u) r): 23 VALU
-        const float w = (-3.0f * q2) * rdu;
-        px = __builtin_fmaf(q3, __builtin_fmaf(w, rx, ux), px);
-        py = __builtin_fmaf(q3, __builtin_fmaf(w, ry, uy), py);
-        pz = __builtin_fmaf(q3, __builtin_fmaf(w, rz, uz), pz);
-    }
+    const float ax[1] = {sx}, ay[1] = {sy}, az[1] = {sz}, bx[1] = {vx}, by[1] = {vy},
+                bz[1] = {vz};
+    pair_vjpN<SPLINE, 1>(ax, ay, az, bx, by, bz, xi, yi, zi, vxi, vyi, vzi, k, px, py, pz);
 }
 
 // Final value of a lane's sum (compensation folded in).
@@ -402,9 +435,24 @@ __device__ __forceinline__ void run_scalar(cfloat *__restrict__ src, cfloat *__r
                 pair_accel<SPLINE>(p[4 * t], p[4 * t + 1], p[4 * t + 2], xs, ys, zs, k, px, py,
                                    pz);
         } else {
-#pragma unroll 2
-            for (int t = 0; t < blk; ++t) {
-                // one 32-byte record per source (offset, cotangent), one scalar load
+            // one 32-byte record per source (offset, cotangent), one scalar load
+            int t = 0;
+            for (; t + 2 <= blk; t += 2) {
+                float ax[2], ay[2], az[2], bx[2], by[2], bz[2];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const rec8 r8 = ((crec8 *)p)[t + u];
+                    ax[u] = r8[0];
+                    ay[u] = r8[1];
+                    az[u] = r8[2];
+                    bx[u] = r8[4];
+                    by[u] = r8[5];
+                    bz[u] = r8[6];
+                }
+                pair_vjpN<SPLINE, 2>(ax, ay, az, bx, by, bz, xs, ys, zs, vi.x, vi.y, vi.z, k, px,
+                                     py, pz);
+            }
+            for (; t < blk; ++t) {
                 const rec8 r8 = ((crec8 *)p)[t];
                 pair_vjp<SPLINE>(r8[0], r8[1], r8[2], r8[4], r8[5], r8[6], xs, ys, zs, vi.x,
                                  vi.y, vi.z, k, px, py, pz);
@@ -587,8 +635,25 @@ __device__ __forceinline__ void segment(const float4 *__restrict__ sx, const flo
                 j += P;
             }
         } else {
-#pragma unroll 4
-            for (int t = 0; t < blk; ++t) {
+            int t = 0;
+            for (; t + 2 <= blk; t += 2) {
+                float ax[2], ay[2], az[2], bx[2], by[2], bz[2];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const float4 s = sx[j + u * P];
+                    const float2 v = sv[j + u * P];
+                    ax[u] = s.x;
+                    ay[u] = s.y;
+                    az[u] = s.z;
+                    bx[u] = s.w;
+                    by[u] = v.x;
+                    bz[u] = v.y;
+                }
+                pair_vjpN<SPLINE, 2>(ax, ay, az, bx, by, bz, xi, yi, zi, vi.x, vi.y, vi.z, k, px,
+                                     py, pz);
+                j += 2 * P;
+            }
+            for (; t < blk; ++t) {
                 const float4 s = sx[j];
                 const float2 v = sv[j];
                 pair_vjp<SPLINE>(s.x, s.y, s.z, s.w, v.x, v.y, xi, yi, zi, vi.x, vi.y, vi.z, k,
