@@ -512,7 +512,12 @@ def main():
     reps = args.steps
     t_plum = ev_time(stream, lambda: nfp.accel(b, 1.0, plummer=True), reps)
     t_full = ev_time(stream, lambda: nfp.accel(b, 1.0, spline_everywhere=True), reps)
-    t_noalloc = ev_time(stream, lambda: nfp.accel_noalloc(b, 1.0, compensated=True), reps)
+    from paper_1810_02916_amd._lib import NfError
+    try:   # the static scratch holds the planner of boxes up to a few million particles
+        t_noalloc, noalloc_skip = ev_time(
+            stream, lambda: nfp.accel_noalloc(b, 1.0, compensated=True), reps), None
+    except NfError as exc:
+        t_noalloc, noalloc_skip = None, str(exc)
     t_sym = ev_time(stream, lambda: nfp.accel(b, 1.0, compensated=True, symmetric=True), reps)
     a_sym = nfp.accel(b, 1.0, compensated=True, symmetric=True)
     t_mom = ev_time(stream, lambda: nfp.multipoles(b, 8), reps)
@@ -534,9 +539,10 @@ def main():
                                         "engaged": not bool(torch.equal(a_sym, a_comp)),
                                         "vs_gather": round(t_comp / t_sym, 4),
                                         "note": "Newton's third law between dense cells"},
-        "accel_compensated_noalloc": {"ms": round(t_noalloc, 4),
-                                      "gdips": round(I / t_noalloc / 1e6, 2),
-                                      "note": "static scratch, the three kernels in turn"},
+        "accel_compensated_noalloc": ({"ms": round(t_noalloc, 4),
+                                       "gdips": round(I / t_noalloc / 1e6, 2),
+                                       "note": "static scratch, the three kernels in turn"}
+                                      if t_noalloc is not None else {"skipped": noalloc_skip}),
         "multipoles_p8": {"ms": round(t_mom, 4), "terms": nfp.multipole_terms(8),
                           "algorithmic_bytes": int(mom_bytes),
                           "hbm_gbs": round(mom_bytes / (t_mom * 1e-3) / 1e9, 1),
