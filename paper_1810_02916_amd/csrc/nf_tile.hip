@@ -375,8 +375,9 @@ __device__ __forceinline__ float3 value(const Acc &a) {
     return make_float3(a.x, a.y, a.z);
 }
 
-__device__ __forceinline__ void store(const DevBox &B, int slot, float3 f) {
-    const int i = gp(B.order)[slot];
+// Scaled result of sorted slot `slot` to caller index i = order[slot] (read
+// by the caller early, so that its latency hides behind the sum).
+__device__ __forceinline__ void store(const DevBox &B, int i, float3 f) {
     if (i >= 0 && i < B.n) {   // always true for a consistent binning
         gptr<float> o = gp(B.out) + 3 * (int64_t)i;
         o[0] = f.x * B.scale;
@@ -500,6 +501,7 @@ k_dense(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
         const bool active = lane < g;
         const int slot = s0 + (active ? lane : 0);
         const float4 oi = ld_global4((gfloat *)B.off, slot);
+        const int dst = gp(B.order)[slot];
         float4 vi = make_float4(0.f, 0.f, 0.f, 0.f);
         if constexpr (MODE == 1) vi = ld_global4((gfloat *)cot_sorted, 2 * (B.base + slot) + 1);
         const Coef k{B.cA, B.cB, B.cC, 2.0f * B.cC, B.eps * B.eps, B.r2floor};
@@ -567,7 +569,7 @@ k_dense(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
                 }
             }
         } else if (active) {
-            store(B, slot, value<COMP>(acc));
+            store(B, dst, value<COMP>(acc));
         }
     }
 }
@@ -743,6 +745,7 @@ k_light(const DevBox *__restrict__ boxes, const Item *__restrict__ all_items,
         const int a = active ? lane % g : 0;
         const int b = active ? lane / g : 0;
         const float4 oi = ld_global4((gfloat *)B.off, s0 + a);
+        const int dst = lane < g ? gp(B.order)[s0 + lane] : 0;   // lane < g stores sink lane
         float4 vi = make_float4(0.f, 0.f, 0.f, 0.f);
         if constexpr (MODE == 1) vi = ld_global4((gfloat *)cot_sorted, 2 * (B.base + s0 + a) + 1);
 
@@ -972,7 +975,7 @@ k_light(const DevBox *__restrict__ boxes, const Item *__restrict__ all_items,
                                 sm.red[2][lane] + sm.red[5][lane]);
             else
                 f = make_float3(sm.red[0][lane], sm.red[1][lane], sm.red[2][lane]);
-            store(B, s0 + lane, f);
+            store(B, dst, f);
         }
         __syncthreads();
         if (lane == 0) {
