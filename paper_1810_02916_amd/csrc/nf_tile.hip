@@ -46,6 +46,9 @@ namespace {
 
 constexpr int kUnit = 64;            // sinks per wave
 constexpr int kQueues = 32;          // light-item queues (a multiple of the 8 XCDs)
+constexpr int kXcds = 8;             // workgroups are dealt to the XCDs round-robin by id
+constexpr int kXcdBlock = 256;       // consecutive light items kept on one XCD
+constexpr int kDenseBlock = 16;      // consecutive dense items kept on one XCD
 constexpr int kQueueStride = 32;     // words between queue counters (own 128-byte line)
 constexpr int kLightWaves = 4;       // waves sharing one light item
 constexpr int kLightThreads = 64 * kLightWaves;
@@ -479,10 +482,18 @@ k_dense(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
     __shared__ int s_item;
     const int lane = threadIdx.x;
     const int nitems = (int)totals[0];
+    // one queue per XCD (workgroup w runs on XCD w % 8): XCD x takes the
+    // blocks of kDenseBlock consecutive items c = x, x + 8, ... in order, so
+    // the chunks of one cell, which share every source, meet in one L2, and
+    // the heaviest items still come first everywhere
+    const int x = (int)(blockIdx.x % kXcds);
+    uint32_t *dq = counter + kQueueStride * x;
     for (;;) {
-        if (lane == 0)
-            s_item = (int)__hip_atomic_fetch_add(gp(counter), 1u, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_AGENT);
+        if (lane == 0) {
+            const int t = (int)__hip_atomic_fetch_add(gp(dq), 1u, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+            s_item = ((t / kDenseBlock) * kXcds + x) * kDenseBlock + t % kDenseBlock;
+        }
         __syncthreads();
         const int itx = uni(s_item);
         __syncthreads();
@@ -701,14 +712,22 @@ k_light(const DevBox *__restrict__ boxes, const Item *__restrict__ all_items,
     const int nitems = (int)totals[cls];
     const gptr<const Item> items = gp(all_items) + (cls == 2 ? totals[1] : 0u);
 
-    // kQueues interleaved queues: workgroup w draws from queue q = w % kQueues,
-    // whose k-th claim is item k * kQueues + q.  A single counter would cap
-    // the item rate at what one address sustains for atomics.
+    // kQueues interleaved queues: workgroup w draws from queue q = w % kQueues
+    // (a single counter would cap the item rate at what one address sustains
+    // for atomics).  The workgroups of queue q run on XCD q % 8, and the
+    // queues of one XCD share blocks of kXcdBlock consecutive items (items
+    // are in spatial order, so neighbours share their sources in that XCD's
+    // L2): XCD x takes the blocks c = x, x + 8, ..., its four queues taking
+    // its items in turn.  (q, k) -> item is one-to-one and increasing in k.
     const int q = (int)(blockIdx.x % kQueues);
     uint32_t *qc = counter + kQueueStride * q;
+    auto queue_item = [q](int kth) {
+        const int t = kth * (kQueues / kXcds) + q / kXcds;   // the XCD's t-th item
+        return ((t / kXcdBlock) * kXcds + q % kXcds) * kXcdBlock + t % kXcdBlock;
+    };
     if (lane == 0) {
-        const int first = (int)__hip_atomic_fetch_add(gp(qc), 1u, __ATOMIC_RELAXED,
-                                                      __HIP_MEMORY_SCOPE_AGENT) * kQueues + q;
+        const int first = queue_item((int)__hip_atomic_fetch_add(gp(qc), 1u, __ATOMIC_RELAXED,
+                                                                 __HIP_MEMORY_SCOPE_AGENT));
         sm.item = first;
         if (first < nitems) {
             sm.ibox = items[first].box;
@@ -725,8 +744,8 @@ k_light(const DevBox *__restrict__ boxes, const Item *__restrict__ all_items,
         // below is done, and both complete while this item runs
         int nxt = 0;
         if (lane == 0)
-            nxt = (int)__hip_atomic_fetch_add(gp(qc), 1u, __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_AGENT) * kQueues + q;
+            nxt = queue_item((int)__hip_atomic_fetch_add(gp(qc), 1u, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT));
         const DevBox &B = boxes[ibox];
         const int K = B.K;
         const int cx = cell0 / (K * K), cy = (cell0 / K) % K, z = cell0 % K;
@@ -1054,7 +1073,7 @@ hipError_t launch_light_inst(const DevBox *d_boxes, const TilePlan &tp, const fl
 template <int MODE, bool COMP>
 hipError_t launch_light(const DevBox *d_boxes, const TilePlan &tp, const float4 *cot,
                         hipStream_t s) {
-    uint32_t *q = tp.counter + kQueueStride;
+    uint32_t *q = tp.counter + kQueueStride * kXcds;
     switch (tp.light_window) {
         case 512: return launch_light_inst<MODE, COMP, 512, kLightThreads>(d_boxes, tp, cot, q, 1, s);
         case 2048:
@@ -1070,7 +1089,7 @@ hipError_t launch_light(const DevBox *d_boxes, const TilePlan &tp, const float4 
 template <int MODE, bool COMP>
 hipError_t launch_narrow(const DevBox *d_boxes, const TilePlan &tp, const float4 *cot,
                          hipStream_t s) {
-    uint32_t *q = tp.counter + kQueueStride * (1 + kQueues);
+    uint32_t *q = tp.counter + kQueueStride * (kXcds + kQueues);
     switch (tp.narrow_window) {
         case 128: return launch_light_inst<MODE, COMP, 128, kNarrowThreads>(d_boxes, tp, cot, q, 2, s);
         case 512:
@@ -1085,7 +1104,9 @@ hipError_t launch_narrow(const DevBox *d_boxes, const TilePlan &tp, const float4
 template <int MODE, bool COMP>
 hipError_t launch_dense(const DevBox *d_boxes, const TilePlan &tp, const float4 *cot,
                         hipStream_t s) {
-    static const int grid = persistent_grid(k_dense<MODE, COMP>, kUnit);
+    // every XCD queue needs at least one workgroup: a multiple of kXcds
+    static const int grid =
+        (persistent_grid(k_dense<MODE, COMP>, kUnit) + kXcds - 1) / kXcds * kXcds;
     hipLaunchKernelGGL((k_dense<MODE, COMP>), dim3(grid), dim3(kUnit), 0, s, d_boxes,
                        (const Item *)tp.dense, (const uint32_t *)tp.totals, tp.counter, cot);
     return hipGetLastError();
@@ -1123,7 +1144,8 @@ hipError_t launch_force(const DevBox *d_boxes, const TilePlan &tp, const float4 
 
 int plan_buckets() { return kKinds * kBuckets; }
 // dense queue, light and narrow queues, then the pair kernel's queue
-int queue_words() { return (2 + 2 * kQueues) * kQueueStride; }
+// dense queues (one per XCD), light queues, narrow queues, the pair kernel's
+int queue_words() { return (kXcds + 2 * kQueues + 1) * kQueueStride; }
 
 hipError_t plan_launch(const DevBox *d_boxes, int nbox, const TilePlan &tp, hipStream_t s) {
     hipError_t e;
