@@ -125,7 +125,16 @@ k_radix_hist(const uint32_t *__restrict__ keys, int64_t N, int shift, int nblk,
     for (int d = t; d < R; d += kSortThreads) hist[(int64_t)d * nblk + blockIdx.x] = cnt[d];
 }
 
-// Stable scatter of one tile.  Wave w owns the contiguous quarter
+// The tile of workgroup b when each of the 8 XCDs (workgroups are dealt to
+// them round-robin by id) takes one contiguous range of the nb tiles.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+    const int x = b % 8, j = b / 8, per = nb / 8, rem = nb % 8;
+    return x * per + min(x, rem) + j;
+}
+
+// Stable scatter of one tile, workgroup b taking tile xcd_tile(b): the
+// neighbouring output runs of a digit (consecutive tiles) then meet whole in
+// one XCD's L2 instead of as line fragments in several.  Wave w owns the contiguous quarter
 // [w*1024, (w+1)*1024) of the tile and walks it in rounds of 64, so
 // "earlier round, then lower lane, then lower wave" is input order; that
 // gives every key its rank within the tile's run of its digit.  The tile is
@@ -153,7 +162,8 @@ k_radix_scatter(const uint32_t *__restrict__ keys_in, const uint32_t *__restrict
     __syncthreads();
 
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const int64_t tile0 = (int64_t)blockIdx.x * kSortTile;
+    const int tile = xcd_tile((int)blockIdx.x, nblk);
+    const int64_t tile0 = (int64_t)tile * kSortTile;
     const int64_t base = tile0 + w * (kSortTile / 4);
     uint32_t kk[kSortItems], vv[kSortItems], rk[kSortItems];
 #pragma unroll
@@ -195,7 +205,7 @@ k_radix_scatter(const uint32_t *__restrict__ keys_in, const uint32_t *__restrict
             const int d = t * DPT + j;
 #pragma unroll
             for (int q = 0; q < 4; ++q) wcnt[q][d] += run;
-            gshift[d] = hist_scan[(int64_t)d * nblk + blockIdx.x] - run;
+            gshift[d] = hist_scan[(int64_t)d * nblk + tile] - run;
             run += tot[j];
         }
     }
