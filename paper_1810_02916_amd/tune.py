@@ -200,6 +200,13 @@ def tune(b, mode: str = "accel", compensated: bool = True, reps: int = 3,
         torch.cuda.synchronize(b.device)
         return e0.elapsed_time(e1) / reps
 
+    # a few untimed calls first: the first candidate timed is otherwise
+    # measured while the clocks still ramp up, which biases the search
+    # against it
+    b.set_tiles(DEFAULTS)
+    for _ in range(4 * reps):
+        call()
+    torch.cuda.synchronize(b.device)
     best, times = search(timer, candidates)
     b.set_tiles(best)
     ms = {_label(t): round(v, 5) for t, v in times.items()}
