@@ -254,6 +254,26 @@ int nf_accel_vjp(int nbox, const nf_box *boxes, double gm, uint32_t flags,
                  size_t ws_bytes, void *stream);
 
 /*
+ * The work list that nf_accel and nf_accel_vjp build before their force
+ * kernels (the near-force work preparation of Sec. 2.2-2.3), without running
+ * them: for inspection, and for callers that schedule the work themselves.
+ * The sinks of every cell are cut into chunks of 64; a chunk is one item of
+ * class 0 (dense: a full chunk, or a last chunk of at least dense_min sinks),
+ * 1 (light: a smaller last chunk) or 2 (narrow: a last chunk of fewer than
+ * narrow_max sinks), with the boxes' tile choices.
+ *   items   device int32 [max_items][4]: (box, cell, chunk, class) of every
+ *           item, dense items first, then light, then narrow, each class in
+ *           the planner's order (inside one cost bucket or spatial slab that
+ *           order may differ between calls; the set of items does not)
+ *   counts  device int64 [3]: the number of items of each class (also those
+ *           beyond max_items, which are not written)
+ * Requires the boxes as filled by nf_bin_particles (cell_start).  ws/ws_bytes
+ * as for nf_accel (nf_workspace_bytes with flags 0).  Errors as for nf_accel.
+ */
+int nf_plan_items(int nbox, const nf_box *boxes, int32_t *items, int64_t max_items,
+                  int64_t *counts, void *ws, size_t ws_bytes, void *stream);
+
+/*
  * Per-cell multipole moments of the binned particles (Sec. 2.1: computed for
  * every cell after the binning, double precision inside, float storage;
  * p = 8 is the paper's usual order).  Basis (the paper does not fix one):

@@ -37,6 +37,7 @@ EXPORTED = (
     "nf_accel",
     "nf_accel_noalloc",
     "nf_accel_vjp",
+    "nf_plan_items",
     "nf_multipoles",
     "nf_step_stats",
     "nf_step_choose",
@@ -102,6 +103,9 @@ def load():
     lib.nf_accel_vjp.restype = ctypes.c_int
     lib.nf_accel_vjp.argtypes = [ctypes.c_int, P, ctypes.c_double, ctypes.c_uint32,
                                  ctypes.POINTER(vp), ctypes.POINTER(vp), vp, ctypes.c_size_t, vp]
+    lib.nf_plan_items.restype = ctypes.c_int
+    lib.nf_plan_items.argtypes = [ctypes.c_int, P, vp, ctypes.c_int64, vp, vp, ctypes.c_size_t,
+                                  vp]
     PP = ctypes.POINTER(vp)
     lib.nf_step_stats.restype = ctypes.c_int
     lib.nf_step_stats.argtypes = [ctypes.c_int, P, PP, PP, PP, PP, vp, vp, ctypes.c_size_t, vp]

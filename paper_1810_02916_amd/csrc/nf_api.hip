@@ -434,6 +434,23 @@ int nf_bin_particles(int nbox, const nf_box *boxes, void *ws, size_t ws_bytes, v
 // noalloc: the workspace is the static `scratch` array of the current device
 // (ws and ws_bytes are ignored), and the force kernels run one after another
 // on the caller's stream (no library side streams or events).
+// The planner's tables inside the workspace.
+static TilePlan tile_plan(const Layout &L, char *w) {
+    TilePlan tp;
+    tp.TG = L.C;
+    tp.max_cells = L.max_ncell;
+    tp.cellinfo = reinterpret_cast<uint32_t *>(w + L.cellinfo_off);
+    tp.bucket_cnt = reinterpret_cast<uint32_t *>(w + L.bucket_off);
+    tp.bucket_off = tp.bucket_cnt + plan_buckets();
+    tp.totals = reinterpret_cast<uint32_t *>(w + L.totals_off);
+    tp.dense = reinterpret_cast<Item *>(w + L.dense_off);
+    tp.light = reinterpret_cast<Item *>(w + L.light_off);
+    tp.counter = reinterpret_cast<uint32_t *>(w + L.counter_off);
+    tp.light_window = L.light_window;
+    tp.narrow_window = L.narrow_window;
+    return tp;
+}
+
 static int force_common(int nbox, const nf_box *boxes, double gm, uint32_t flags,
                         const float *const *cot, float *const *out, void *ws, size_t ws_bytes,
                         void *stream, bool vjp, bool noalloc = false) {
@@ -523,18 +540,7 @@ static int force_common(int nbox, const nf_box *boxes, double gm, uint32_t flags
     if (p.simple || L.N == 0) {
         e = vjp ? vjp_launch(d_tab, nbox, p, s) : accel_launch(d_tab, nbox, p, s);
     } else {
-        TilePlan tp;
-        tp.TG = L.C;
-        tp.max_cells = L.max_ncell;
-        tp.cellinfo = reinterpret_cast<uint32_t *>(w + L.cellinfo_off);
-        tp.bucket_cnt = reinterpret_cast<uint32_t *>(w + L.bucket_off);
-        tp.bucket_off = tp.bucket_cnt + plan_buckets();
-        tp.totals = reinterpret_cast<uint32_t *>(w + L.totals_off);
-        tp.dense = reinterpret_cast<Item *>(w + L.dense_off);
-        tp.light = reinterpret_cast<Item *>(w + L.light_off);
-        tp.counter = reinterpret_cast<uint32_t *>(w + L.counter_off);
-        tp.light_window = L.light_window;
-        tp.narrow_window = L.narrow_window;
+        const TilePlan tp = tile_plan(L, w);
         e = vjp ? gather_cot_launch(d_tab, nbox, p, s) : hipSuccess;
         if (e == hipSuccess) e = plan_launch(d_tab, nbox, tp, s);
         if (e == hipSuccess && use_f4) e = f4_plan_launch(d_tab, nbox, fp, s);
@@ -572,6 +578,35 @@ int nf_accel_vjp(int nbox, const nf_box *boxes, double gm, uint32_t flags,
                  void *stream) {
     try {
         return force_common(nbox, boxes, gm, flags, cot, grad, ws, ws_bytes, stream, true);
+    } catch (...) {
+        return fail(NF_EINVAL, "internal error");
+    }
+}
+
+int nf_plan_items(int nbox, const nf_box *boxes, int32_t *items, int64_t max_items,
+                  int64_t *counts, void *ws, size_t ws_bytes, void *stream) {
+    try {
+        Layout L;
+        int rc = validate(nbox, boxes, L);
+        if (rc) return rc;
+        if (!counts) return fail(NF_EINVAL, "counts is NULL");
+        if (max_items < 0) return fail(NF_EINVAL, "max_items < 0");
+        if (max_items > 0 && !items) return fail(NF_EINVAL, "items is NULL");
+        if ((rc = check_ws(L, ws, ws_bytes))) return rc;
+        std::string why;
+        if ((rc = check_device(why))) return fail(rc, why);
+        char *w = static_cast<char *>(ws);
+        std::vector<DevBox> tab((size_t)nbox);
+        for (int b = 0; b < nbox; ++b) fill_geometry(boxes[b], L, b, tab[b]);
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        DevBox *d_tab = reinterpret_cast<DevBox *>(w + L.table_off);
+        hipError_t e = upload(tab.data(), sizeof(DevBox) * tab.size(), d_tab, s);
+        const TilePlan tp = tile_plan(L, w);
+        if (e == hipSuccess) e = plan_launch(d_tab, nbox, tp, s);
+        if (e == hipSuccess) e = plan_export_launch(tp, items, max_items, counts, s);
+        if (e != hipSuccess) return fail(NF_EHIP, std::string("plan launch: ") + hipGetErrorString(e));
+        g_last_error.clear();
+        return NF_OK;
     } catch (...) {
         return fail(NF_EINVAL, "internal error");
     }

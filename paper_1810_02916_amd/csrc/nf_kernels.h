@@ -68,6 +68,10 @@ struct TilePlan {
 int plan_buckets();
 int queue_words();
 hipError_t plan_launch(const DevBox *d_boxes, int nbox, const TilePlan &tp, hipStream_t s);
+// The planned items as (box, cell, chunk, class) int32 quadruples, dense,
+// light then narrow, at most max_items of them, and the three class counts.
+hipError_t plan_export_launch(const TilePlan &tp, int32_t *items, int64_t max_items,
+                              int64_t *counts, hipStream_t s);
 // mode 0: accelerations, 1: VJP (cot = cotangents in sorted order).
 // concurrent: the light and narrow kernels run on the library's side streams
 // alongside the dense kernel; otherwise all three run in turn on s.

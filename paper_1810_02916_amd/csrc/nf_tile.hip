@@ -1147,6 +1147,38 @@ int plan_buckets() { return kKinds * kBuckets; }
 // dense queues (one per XCD), light queues, narrow queues, the pair kernel's
 int queue_words() { return (kXcds + 2 * kQueues + 1) * kQueueStride; }
 
+namespace {
+__global__ void __launch_bounds__(256)
+k_plan_export(const uint32_t *__restrict__ totals, const Item *__restrict__ dense,
+              const Item *__restrict__ light, int32_t *__restrict__ out, int64_t max_items,
+              int64_t *__restrict__ counts) {
+    const int64_t nd = totals[0], nl = totals[1], nn = totals[2];
+    const int64_t total = min(nd + nl + nn, max_items);
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < 3) counts[t] = t == 0 ? nd : (t == 1 ? nl : nn);
+    for (int64_t i = t; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        // narrow items follow the light ones in the same array
+        const Item it = i < nd ? dense[i] : light[i - nd];
+        const int32_t cls = i < nd ? 0 : (i < nd + nl ? 1 : 2);
+        int32_t *o = out + 4 * i;
+        o[0] = it.box;
+        o[1] = it.cell0;
+        o[2] = it.chunk;
+        o[3] = cls;
+    }
+}
+}  // namespace
+
+hipError_t plan_export_launch(const TilePlan &tp, int32_t *items, int64_t max_items,
+                              int64_t *counts, hipStream_t s) {
+    const unsigned blocks = (unsigned)std::max<int64_t>(
+        1, std::min<int64_t>(4096, (max_items + 255) / 256));
+    hipLaunchKernelGGL(k_plan_export, dim3(blocks), dim3(256), 0, s,
+                       (const uint32_t *)tp.totals, (const Item *)tp.dense,
+                       (const Item *)tp.light, items, max_items, counts);
+    return hipGetLastError();
+}
+
 hipError_t plan_launch(const DevBox *d_boxes, int nbox, const TilePlan &tp, hipStream_t s) {
     hipError_t e;
     dim3 grid((unsigned)((tp.max_cells + 255) / 256), (unsigned)nbox);

@@ -132,11 +132,15 @@ class Binned:
     def tiles(self) -> Tiles:
         return self.boxes[0].tiles
 
-    def set_tiles(self, tiles: Tiles) -> None:
-        """Change the force kernels' tile choices for all boxes; the
+    def set_tiles(self, tiles) -> None:
+        """Change the force kernels' tile choices: one ``Tiles`` for all
+        boxes, or a sequence of one per box (the windows must agree); the
         workspace grows if the new choices need more."""
-        for bx in self.boxes:
-            bx.tiles = tiles
+        per_box = [tiles] * self.nbox if isinstance(tiles, Tiles) else list(tiles)
+        if len(per_box) != self.nbox:
+            raise ValueError("one Tiles per box is required")
+        for bx, t in zip(self.boxes, per_box):
+            bx.tiles = t
         self._arr = None
         need = _lib.load().nf_workspace_bytes(self.nbox, self.carray(), 0)
         if need == 0:
@@ -307,6 +311,25 @@ def accel_noalloc(b: Binned, gm: float = 1.0, *, compensated: bool = False,
                                   _ptr_array(out), _stream_handle(b.device))
     _lib.check(rc)
     return out[0] if b.nbox == 1 else out
+
+
+def plan_items(b: Binned):
+    """The work list of the force calls (nf_plan_items): an int32 tensor
+    [m, 4] of (box, cell, chunk, class) on the device, dense items (class 0)
+    first, then light (1), then narrow (2), and the three class counts."""
+    lib = _lib.load()
+    # a cell of n sinks gives at most n / 64 + 1 items
+    cap = sum(bx.n // 64 + bx.K ** 3 for bx in b.boxes)
+    items = torch.empty((max(cap, 1), 4), dtype=torch.int32, device=b.device)
+    counts = torch.zeros(3, dtype=torch.int64, device=b.device)
+    with torch.cuda.device(b.device):
+        rc = lib.nf_plan_items(b.nbox, b.carray(), ctypes.c_void_p(items.data_ptr()), cap,
+                               ctypes.c_void_p(counts.data_ptr()),
+                               ctypes.c_void_p(b.workspace.data_ptr()), b.workspace.numel(),
+                               _stream_handle(b.device))
+    _lib.check(rc)
+    c = [int(x) for x in counts.cpu()]
+    return items[:sum(c)], tuple(c)
 
 
 def accel_vjp(b: Binned, cot, gm: float = 1.0, *, compensated: bool = False,
