@@ -485,7 +485,8 @@ k_dense(const DevBox *__restrict__ boxes, const Item *__restrict__ items,
     // one queue per XCD (workgroup w runs on XCD w % 8): XCD x takes the
     // blocks of kDenseBlock consecutive items c = x, x + 8, ... in order, so
     // the chunks of one cell, which share every source, meet in one L2, and
-    // the heaviest items still come first everywhere
+    // the heaviest items still come first everywhere (the map is one-to-one
+    // and increasing, so only the locality depends on the placement)
     const int x = (int)(blockIdx.x % kXcds);
     uint32_t *dq = counter + kQueueStride * x;
     for (;;) {
@@ -718,7 +719,9 @@ k_light(const DevBox *__restrict__ boxes, const Item *__restrict__ all_items,
     // queues of one XCD share blocks of kXcdBlock consecutive items (items
     // are in spatial order, so neighbours share their sources in that XCD's
     // L2): XCD x takes the blocks c = x, x + 8, ..., its four queues taking
-    // its items in turn.  (q, k) -> item is one-to-one and increasing in k.
+    // its items in turn.  (q, k) -> item is one-to-one and increasing in k,
+    // so the results do not depend on where the workgroups actually run;
+    // only the L2 locality does.
     const int q = (int)(blockIdx.x % kQueues);
     uint32_t *qc = counter + kQueueStride * q;
     auto queue_item = [q](int kth) {
