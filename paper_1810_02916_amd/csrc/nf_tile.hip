@@ -605,6 +605,8 @@ struct LightSmem {
     int rs[128];                     // staged start of each non-empty piece (run), ascending,
                                      // then INT_MAX
     float4 rd[kPiece];               // per run: (global minus staged index, dx, dy, z bias)
+    uint32_t bm[CAP / 32];           // staging window: bit e set when a run starts at u0 + e
+    int cum[CAP / 32];               // runs starting before word w of the window
     int item;                        // current item and its (box, cell)
     int ibox, icell, ichunk;
     int inner;                       // staged particles of the 27 inner cells
@@ -877,25 +879,48 @@ k_light(const DevBox *__restrict__ boxes, const Item *__restrict__ all_items,
         const int inner = uni(sm.inner);
         const bool single = total <= CAP;
 
-        // stage the union window [u0, u1): thread t takes elements u0 + t + NT i,
-        // finds their runs by a branch-free 7-step binary search over the run
-        // starts (padded with INT_MAX), the searches of its elements interleaved,
-        // and issues all its loads before any LDS store
+        // stage the union window [u0, u1): thread t takes elements u0 + t + NT i.
+        // Wave 0 first marks the run starts inside the window in a bitmap and
+        // counts, per 32-element word, the runs that start before it; the run
+        // of element d is then (runs starting at or before d) - 1, one word
+        // lookup and a popcount.  Every thread issues all its loads before
+        // any LDS store.
         auto stage = [&](int u0, int u1) {
             constexpr int kPer = CAP / NT;
+            constexpr int kWords = CAP / 32;
+            static_assert(CAP % 32 == 0 && kWords <= 64, "one bitmap word per lane of wave 0");
+            if (lane < 64) {
+                if (lane < kWords) sm.bm[lane] = 0u;
+                __builtin_amdgcn_wave_barrier();
+                int before = 0;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int v = sm.rs[lane + 64 * h];   // INT_MAX past the last run
+                    if (v < u0)
+                        ++before;
+                    else if (v < u1)
+                        atomicOr(&sm.bm[(v - u0) >> 5], 1u << ((v - u0) & 31));
+                }
+                __builtin_amdgcn_wave_barrier();
+                const int kb = (int)__popcll(__ballot(before >= 1)) +
+                               (int)__popcll(__ballot(before >= 2));
+                const int c = lane < kWords ? __popc(sm.bm[lane]) : 0;
+                int x = c;
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int y = __shfl_up(x, o);
+                    if (lane >= o) x += y;
+                }
+                if (lane < kWords) sm.cum[lane] = kb + x - c;
+            }
+            __syncthreads();
             int pos[kPer], d[kPer];
 #pragma unroll
             for (int i = 0; i < kPer; ++i) {
-                pos[i] = 0;
                 d[i] = u0 + lane + NT * i;
-            }
-#pragma unroll
-            for (int st = 64; st > 0; st >>= 1) {
-#pragma unroll
-                for (int i = 0; i < kPer; ++i) {
-                    const int c = pos[i] + st;
-                    pos[i] = sm.rs[c] <= d[i] ? c : pos[i];
-                }
+                const int e = lane + NT * i;   // < CAP
+                const uint32_t w = sm.bm[e >> 5];
+                pos[i] = sm.cum[e >> 5] + __popc(w & (0xffffffffu >> (31 - (e & 31)))) - 1;
             }
             float4 buf[kPer], cb[kPer];
             float sh[kPer][3];
