@@ -23,7 +23,7 @@ After the timed steps the same line carries, untimed by ``value``:
   * the widened rows (Plummer law, multipoles, step statistics and choice,
     kick/drift).
 
-Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
+Prints one JSON line.  --gpus above 1 is refused: the benchmark runs on one GPU.
 """
 from __future__ import annotations
 
@@ -39,7 +39,9 @@ if ROOT not in sys.path:
 
 # Algorithmic work per pair interaction.
 FLOP_ACCEL = 23    # the paper's count: 22 add/mul + rsqrt as one (Sec. 2.3)
-FLOP_VJP = 36      # the adjoint's operation list
+# the adjoint's operation list: r (3 sub), v_j - v_i (3 sub), r^2 (5), rsqrt
+# (1), q^2 and q^3 (2), r.dv (5), h (2), t (1), accumulation (12), spline (2)
+FLOP_VJP = 36
 PEAK_FP32 = 157.3e12
 PEAK_HBM = 8.0e12
 METRIC = "G pair-interactions/s and particles/s (FP32 vs compensated, err vs FP64)"
@@ -430,7 +432,7 @@ def rec_clustered134m(args, stream, with_cpu: bool) -> dict:
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU; multi-GPU runs are not part of this build",
+        print("bench.py runs on exactly one GPU; multi-GPU runs are not supported",
               file=sys.stderr)
         sys.exit(2)
 

@@ -82,7 +82,7 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(
             f"{LIB_PATH} is missing: build the HIP library first "
-            "(python -c 'import __graft_entry__ as g; g.build()')")
+            "(python -c 'from paper_1810_02916_amd import build; build.build()')")
     lib = ctypes.CDLL(LIB_PATH)
     vp = ctypes.c_void_p
     P = ctypes.POINTER(NfBox)
