@@ -299,19 +299,21 @@ __device__ __forceinline__ void pair_accel4(const float (&sx)[4], const float (&
 }
 
 // N pairs of the VJP, added in order: xbar_i += g (v_j - v_i) + h (r .
-// (v_j - v_i)) r, with g = F/r and h = g'(rho)/rho.  Outside eps (Newton, or
-// Plummer through the r^2 floor) g = q^3 and h = -3 q^5, so the term is
-// q^3 (u - 3 q^2 (r.u) r): 23 VALU.  Inside eps g = cA + cB rho + cC rho^2
-// and h = cB / rho + 2 cC = cB q + 2 cC.  With SPLINE the inside form is
-// evaluated only when some lane of the wave has one of the N pairs inside
-// eps (a compare per pair otherwise), as in pair_accel.
+// (v_j - v_i)) r, with g = F/r and h = g'(rho)/rho, written as
+// xbar_i += A (u + W r) with u = v_j - v_i, A = g and W = h (r . u) / g.
+// Outside eps (Newton, or Plummer through the r^2 floor) A = q^3 and
+// W = -3 q^2 (r . u): 23 VALU.  Inside eps g = cA + cB rho + cC rho^2 > 0 and
+// h = cB / rho + 2 cC = cB q + 2 cC.  With SPLINE the inside coefficients
+// replace the Newton ones only when some lane of the wave has one of the N
+// pairs inside eps (a compare per pair otherwise), as in pair_accel; the
+// branch rewrites A and W only, so the sums are updated outside it.
 template <bool SPLINE, int N>
 __device__ __forceinline__ void pair_vjpN(const float (&sx)[N], const float (&sy)[N],
                                           const float (&sz)[N], const float (&vx)[N],
                                           const float (&vy)[N], const float (&vz)[N], float xi,
                                           float yi, float zi, float vxi, float vyi, float vzi,
                                           const Coef &k, float &px, float &py, float &pz) {
-    float rx[N], ry[N], rz[N], ux[N], uy[N], uz[N], r2[N], q[N], rdu[N];
+    float rx[N], ry[N], rz[N], ux[N], uy[N], uz[N], r2[N], q[N], rdu[N], A[N], W[N];
     bool in = false;
 #pragma unroll
     for (int u = 0; u < N; ++u) {
@@ -328,37 +330,31 @@ __device__ __forceinline__ void pair_vjpN(const float (&sx)[N], const float (&sy
         rdu[u] = rx[u] * ux[u];
         rdu[u] = __builtin_fmaf(ry[u], uy[u], rdu[u]);
         rdu[u] = __builtin_fmaf(rz[u], uz[u], rdu[u]);
+        const float q2 = q[u] * q[u];
+        A[u] = q2 * q[u];
+        W[u] = (-3.0f * q2) * rdu[u];
         if constexpr (SPLINE) in |= r2[u] < k.eps2;
     }
-    auto newton = [&](int u, float &ax, float &ay, float &az) {
-        const float q2 = q[u] * q[u];
-        const float q3 = q2 * q[u];
-        const float w = (-3.0f * q2) * rdu[u];
-        ax = __builtin_fmaf(q3, __builtin_fmaf(w, rx[u], ux[u]), ax);
-        ay = __builtin_fmaf(q3, __builtin_fmaf(w, ry[u], uy[u]), ay);
-        az = __builtin_fmaf(q3, __builtin_fmaf(w, rz[u], uz[u]), az);
-    };
     if constexpr (SPLINE) {
         if (__any(in)) {
             asm volatile("");   // keep the rare branch a branch
 #pragma unroll
             for (int u = 0; u < N; ++u) {
-                float nx = px, ny = py, nz = pz;
-                newton(u, nx, ny, nz);
                 const float rho = r2[u] * q[u];
                 const float g = __builtin_fmaf(__builtin_fmaf(k.cC, rho, k.cB), rho, k.cA);
                 const float h = __builtin_fmaf(k.cB, q[u], k.cC2);
-                const float t = h * rdu[u];
                 const bool inside = r2[u] < k.eps2;
-                px = inside ? __builtin_fmaf(t, rx[u], __builtin_fmaf(g, ux[u], px)) : nx;
-                py = inside ? __builtin_fmaf(t, ry[u], __builtin_fmaf(g, uy[u], py)) : ny;
-                pz = inside ? __builtin_fmaf(t, rz[u], __builtin_fmaf(g, uz[u], pz)) : nz;
+                A[u] = inside ? g : A[u];
+                W[u] = inside ? (h * rdu[u]) / g : W[u];
             }
-            return;
         }
     }
 #pragma unroll
-    for (int u = 0; u < N; ++u) newton(u, px, py, pz);
+    for (int u = 0; u < N; ++u) {
+        px = __builtin_fmaf(A[u], __builtin_fmaf(W[u], rx[u], ux[u]), px);
+        py = __builtin_fmaf(A[u], __builtin_fmaf(W[u], ry[u], uy[u]), py);
+        pz = __builtin_fmaf(A[u], __builtin_fmaf(W[u], rz[u], uz[u]), pz);
+    }
 }
 
 template <bool SPLINE>
