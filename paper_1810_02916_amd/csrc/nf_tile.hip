@@ -58,6 +58,24 @@ constexpr int kRows = 25;            // (dx, dy) rows of the 5x5x5 block
 __device__ __forceinline__ int wrapk(int c, int K) { return c < 0 ? c + K : (c >= K ? c - K : c); }
 __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
+// Inclusive prefix sums over the lanes of a wave (all 64 lanes active): a
+// Kogge-Stone scan inside each row of 16 lanes by DPP row shifts (one
+// v_add_u32_dpp per step), then the row totals read back with readlane.
+// scan_lanes<32> is exact on lanes 0..31 only.
+template <int W>
+__device__ __forceinline__ int scan_lanes(int x) {
+    static_assert(W == 32 || W == 64, "one or two halves of the wave");
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);   // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);   // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);   // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);   // row_shr:8
+    const int row = (threadIdx.x & 63) >> 4;
+    const int t15 = __builtin_amdgcn_readlane(x, 15);
+    if constexpr (W == 32) return x + ((row & 1) ? t15 : 0);
+    const int t31 = __builtin_amdgcn_readlane(x, 31), t47 = __builtin_amdgcn_readlane(x, 47);
+    return x + (row >= 1 ? t15 : 0) + (row >= 2 ? t31 : 0) + (row >= 3 ? t47 : 0);
+}
+
 // ------------------------------------------------------------------ planner
 
 // Sources in the 5x5x5 block of cell (cx, cy, cz): 25 row ranges of 5 cells.
@@ -822,18 +840,11 @@ k_light(const DevBox *__restrict__ boxes, const Item *__restrict__ all_items,
             // the non-empty piece counts (inner | outer << 16), by a wave scan
             const int ca = pn[0] + pn[1], ce = pn[2] + pn[3];
             const int cn = ((pn[0] > 0) + (pn[1] > 0)) | (((pn[2] > 0) + (pn[3] > 0)) << 16);
-            int ia = ca, ie = ce, in_ = cn;
-#pragma unroll
-            for (int o = 1; o < 32; o <<= 1) {
-                const int ta = __shfl_up(ia, o), te = __shfl_up(ie, o), tn = __shfl_up(in_, o);
-                if (r >= o) {
-                    ia += ta;
-                    ie += te;
-                    in_ += tn;
-                }
-            }
-            const int tin = __shfl(ia, kRows - 1), tout = __shfl(ie, kRows - 1);
-            const int tn = __shfl(in_, kRows - 1);
+            static_assert(kRows <= 32, "the row scans use lanes 0..31");
+            const int ia = scan_lanes<32>(ca), ie = scan_lanes<32>(ce), in_ = scan_lanes<32>(cn);
+            const int tin = __builtin_amdgcn_readlane(ia, kRows - 1);
+            const int tout = __builtin_amdgcn_readlane(ie, kRows - 1);
+            const int tn = __builtin_amdgcn_readlane(in_, kRows - 1);
             const int kin = tn & 0xffff, kout = tn >> 16;
             if (r < kRows) {
                 const int n0 = in_ - cn;
@@ -901,12 +912,7 @@ k_light(const DevBox *__restrict__ boxes, const Item *__restrict__ all_items,
                 const int kb = (int)__popcll(__ballot(before >= 1)) +
                                (int)__popcll(__ballot(before >= 2));
                 const int c = lane < kWords ? __popc(sm.bm[lane]) : 0;
-                int x = c;
-#pragma unroll
-                for (int o = 1; o < 64; o <<= 1) {
-                    const int y = __shfl_up(x, o);
-                    if (lane >= o) x += y;
-                }
+                const int x = scan_lanes<(kWords <= 32 ? 32 : 64)>(c);
                 if (lane < kWords) sm.cum[lane] = kb + x - c;
             }
             __syncthreads();
