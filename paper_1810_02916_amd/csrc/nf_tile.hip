@@ -430,7 +430,8 @@ __device__ __forceinline__ void run_scalar(cfloat *__restrict__ src, cfloat *__r
     cfloat *p = src + (int64_t)W * j0;
     int j = j0;
     while (j < j1) {
-        const int blk = min(j1 - j, flush);
+        // compensated: plain partials of at most flush terms; plain: one run
+        const int blk = COMP ? min(j1 - j, flush) : j1 - j;
         float px = 0.f, py = 0.f, pz = 0.f;
         if constexpr (!COMP) {
             px = acc.x;
@@ -638,7 +639,8 @@ __device__ __forceinline__ void segment(const float4 *__restrict__ sx, const flo
     int j = lo + b;
     int it = 0;
     while (it < nfull) {
-        const int blk = min(nfull - it, flush);
+        // compensated: plain partials of at most flush terms; plain: one run
+        const int blk = COMP ? min(nfull - it, flush) : nfull - it;
         float px = 0.f, py = 0.f, pz = 0.f;
         if constexpr (!COMP) {
             px = acc.x;
