@@ -89,7 +89,7 @@ struct Layout {
     size_t hist_off = 0, cellcnt_off = 0, scan_off = 0;
     size_t cot_off = 0, cellinfo_off = 0, bucket_off = 0, totals_off = 0, dense_off = 0,
            light_off = 0, counter_off = 0;
-    size_t stepio_off = 0, cellstat_off = 0, partial_off = 0;
+    size_t stepio_off = 0, cellstat_off = 0, partial_off = 0, partstat_off = 0;
     size_t mp_base_off = 0, mp_first_off = 0, mp_first_bytes = 0;
     size_t mp_npieces_off = 0, mp_scan_off = 0, mp_pieces_off = 0, mp_partial_off = 0;
     int64_t mp_max_pieces = 0;
@@ -248,6 +248,8 @@ int validate(int nbox, const nf_box *boxes, Layout &L, uint32_t flags = 0) {
     o = align_up(o + sizeof(CellStat) * (size_t)L.C, 256);
     L.partial_off = o;
     o = align_up(o + sizeof(CellStat) * (size_t)kStepBlocks * (size_t)nbox, 256);
+    L.partstat_off = o;
+    o = align_up(o + sizeof(PartStat) * (size_t)L.N, 256);
     const size_t step_end = o;
     // multipole partition, also over the binning scratch region
     o = scratch0;
@@ -653,7 +655,8 @@ int nf_step_stats(int nbox, const nf_box *boxes, const float *const *acc,
         StepIO *d_io = nullptr;
         if ((rc = step_common(nbox, boxes, io, ws, ws_bytes, s, L, d_tab, d_io))) return rc;
         char *w = static_cast<char *>(ws);
-        hipError_t e = step_stats_launch(d_tab, d_io, nbox, L.max_ncell,
+        hipError_t e = step_stats_launch(d_tab, d_io, nbox, L.max_n, L.max_ncell,
+                                         reinterpret_cast<PartStat *>(w + L.partstat_off),
                                          reinterpret_cast<CellStat *>(w + L.cellstat_off),
                                          reinterpret_cast<CellStat *>(w + L.partial_off), glob, s);
         if (e != hipSuccess) return fail(NF_EHIP, std::string("step stats: ") + hipGetErrorString(e));

@@ -122,10 +122,13 @@ struct StepChoice {             // the caller's constants of the step choice
 struct CellStat {               // per cell: max |a|, sum |v|^2, max |v|^2
     double amax, v2sum, vmax2;
 };
+struct PartStat {               // per particle, caller order: |a| and |v|^2
+    double a, v2;
+};
 constexpr int kStepBlocks = 256;   // partial reductions per box (power of two)
 hipError_t step_stats_launch(const DevBox *d_boxes, const StepIO *d_io, int nbox,
-                             int64_t max_ncell, CellStat *scratch, CellStat *partial,
-                             double *glob, hipStream_t s);
+                             int64_t max_n, int64_t max_ncell, PartStat *part,
+                             CellStat *scratch, CellStat *partial, double *glob, hipStream_t s);
 hipError_t step_choose_launch(const DevBox *d_boxes, const StepIO *d_io, int nbox,
                               double *partial, const double *glob, const StepChoice &ch,
                               double *bounds, hipStream_t s);

@@ -4,6 +4,10 @@
 // the fastest particle crosses 80% of a cell; the step's Kick and Drift
 // stages).
 //
+//   k_step_parts   caller order, streaming: each particle's |a| and |v|^2
+//                  (double) into one 16-byte record, so that the cell pass
+//                  gathers one record per particle instead of two 12-byte
+//                  vectors from two arrays;
 //   k_step_cells   a wave per 8 consecutive cells over the cell-sorted
 //                  slots: 8 lanes per cell when none of them holds more than
 //                  64 particles, else the whole wave for each in turn; a_max
@@ -52,24 +56,36 @@ __device__ __forceinline__ double group_max(double x) {
     return x;
 }
 
+// |a| and |v|^2 of every particle of the box, in caller order.
+__global__ void __launch_bounds__(256)
+k_step_parts(const DevBox *__restrict__ boxes, const StepIO *__restrict__ io,
+             PartStat *__restrict__ part) {
+#pragma clang fp contract(off)
+    const DevBox &B = boxes[blockIdx.y];
+    const StepIO &S = io[blockIdx.y];
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= B.n) return;
+    const float *a = S.acc + 3 * (int64_t)i;
+    const float *v = S.vel + 3 * (int64_t)i;
+    part[B.base + i] = PartStat{__dsqrt_rn(dsq3(a[0], a[1], a[2])), dsq3(v[0], v[1], v[2])};
+}
+
 // Statistics of cell c over its slots [s0, s1), taken by the W lanes of a
 // group lane-strided (q = the lane's index in the group), then reduced by
 // the group's butterfly; lane q == 0 writes them.
 template <int W>
-__device__ __forceinline__ void cell_stats(const DevBox &B, const StepIO &S, CellStat *scratch,
+__device__ __forceinline__ void cell_stats(const DevBox &B, const StepIO &S,
+                                           const PartStat *__restrict__ part, CellStat *scratch,
                                            int c, int s0, int s1, int q, bool valid) {
 #pragma clang fp contract(off)
     double am = 0.0, v2 = 0.0, vm = 0.0;
     for (int s = s0 + q; s < s1; s += W) {
         const int i = B.order[s];
         if (i < 0 || i >= B.n) continue;   // never taken for a consistent binning
-        const float *a = S.acc + 3 * (int64_t)i;
-        const float *v = S.vel + 3 * (int64_t)i;
-        const double a2 = dsq3(a[0], a[1], a[2]);
-        const double w2 = dsq3(v[0], v[1], v[2]);
-        am = fmax(am, __dsqrt_rn(a2));
-        v2 = v2 + w2;
-        vm = fmax(vm, w2);
+        const PartStat r = part[B.base + i];
+        am = fmax(am, r.a);
+        v2 = v2 + r.v2;
+        vm = fmax(vm, r.v2);
     }
     am = group_max<W>(am);
     v2 = group_sum<W>(v2);
@@ -84,7 +100,7 @@ __device__ __forceinline__ void cell_stats(const DevBox &B, const StepIO &S, Cel
 
 __global__ void __launch_bounds__(kStatThreads)
 k_step_cells(const DevBox *__restrict__ boxes, const StepIO *__restrict__ io,
-             CellStat *__restrict__ scratch) {
+             const PartStat *__restrict__ part, CellStat *__restrict__ scratch) {
 #pragma clang fp contract(off)
     const DevBox &B = boxes[blockIdx.y];
     const StepIO &S = io[blockIdx.y];
@@ -97,11 +113,11 @@ k_step_cells(const DevBox *__restrict__ boxes, const StepIO *__restrict__ io,
         const bool valid = c < B.ncell;
         const int s0 = valid ? cs[c] : 0, s1 = valid ? cs[c + 1] : 0;
         if (__all(s1 - s0 <= kGroupMax)) {
-            cell_stats<kGroup>(B, S, scratch, c, s0, s1, lane % kGroup, valid);
+            cell_stats<kGroup>(B, S, part, scratch, c, s0, s1, lane % kGroup, valid);
         } else {   // a big cell among the eight: each cell by the whole wave
             for (int k = 0; k < kGroup && cb + k < B.ncell; ++k) {
                 const int cc = cb + k;
-                cell_stats<64>(B, S, scratch, cc, cs[cc], cs[cc + 1], lane, true);
+                cell_stats<64>(B, S, part, scratch, cc, cs[cc], cs[cc + 1], lane, true);
             }
         }
     }
@@ -244,14 +260,19 @@ k_kick_drift(const DevBox *__restrict__ boxes, const StepIO *__restrict__ io, do
 }  // namespace
 
 hipError_t step_stats_launch(const DevBox *d_boxes, const StepIO *d_io, int nbox,
-                             int64_t max_ncell, CellStat *scratch, CellStat *partial,
-                             double *glob, hipStream_t s) {
+                             int64_t max_n, int64_t max_ncell, PartStat *part,
+                             CellStat *scratch, CellStat *partial, double *glob, hipStream_t s) {
+    hipError_t e;
+    if (max_n > 0) {
+        hipLaunchKernelGGL(k_step_parts, dim3((unsigned)((max_n + 255) / 256), (unsigned)nbox),
+                           dim3(256), 0, s, d_boxes, d_io, part);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     const int64_t nb = (max_ncell + kStatWaves * kGroup - 1) / (kStatWaves * kGroup);
     const unsigned gx = (unsigned)std::max<int64_t>(1, std::min<int64_t>(nb, 8192));
     hipLaunchKernelGGL(k_step_cells, dim3(gx, (unsigned)nbox), dim3(kStatThreads), 0, s, d_boxes,
-                       d_io, scratch);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+                       d_io, (const PartStat *)part, scratch);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_step_partial, dim3(kStepBlocks, (unsigned)nbox), dim3(kStatThreads), 0, s,
                        d_boxes, (const CellStat *)scratch, partial);
     if ((e = hipGetLastError()) != hipSuccess) return e;
